@@ -1,0 +1,187 @@
+"""Benchmark of the random-phase Trotter path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--prec c64|c128|both] [--no-cpu-baseline]
+
+Default workload: the 2 x 15 XY spin ladder (M = 30 sites, 43 couplings,
+J = 1 on legs and rungs), dt = 0.05, site 0 polarised and observed, one
+random-phase state (seed 5).  A bench "step" is one symmetric Trotter step
+of the whole path (every pass of that step, with the observable fused).
+Inputs are resident in HBM when the timed region starts; the timed region
+is one spin_trotter_evolve call of K steps, bracketed by HIP events on the
+stream the kernels run on.
+
+value  = amplitude updates per second of the complex64 (FP32) path,
+         2 K_c 2^M per Trotter step (each half-step factor counts once).
+Also reported: the complex128 (FP64) path, the FP32-vs-FP64 error of P,
+the pass kernel's roofline numbers and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitude-updates/s + HBM GB/s per Trotter step at M=30, FP32 vs FP64 at stated err"
+HBM_PEAK_GBS = 8000.0
+
+
+def ladder_workload():
+    import workloads
+    L, dt, steps, seed = workloads.LADDER_CONFIGS["ladder_2x15"]
+    return dict(name="ladder_2x15_xy", M=2 * L, J=workloads.ladder(L), dt=dt, steps=steps, seed=seed,
+                observed=0, polarized=0)
+
+
+def run_path(spq, torch, w, prec, steps, warmup):
+    """Returns dict with timing, P (host) and plan info for one precision."""
+    M, J, dt = w["M"], w["J"], w["dt"]
+    dtype = torch.complex64 if prec == spq.SPIN_C64 else torch.complex128
+    psi = torch.empty(2 ** M, dtype=dtype, device="cuda")
+    P = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+    N = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+    Pw = torch.empty(max(warmup, 0) + 1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    if warmup > 0:
+        spq.spin_init_random_phase(psi, M, w["polarized"], w["seed"])
+        spq.spin_trotter_evolve(psi, M, J, dt, warmup, w["observed"], Pw)
+    spq.spin_init_random_phase(psi, M, w["polarized"], w["seed"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    spq.spin_trotter_evolve(psi, M, J, dt, steps, w["observed"], P, N)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    info = spq.spin_describe_plan(prec, M, J, dt, steps, w["observed"])
+    out = dict(ms_total=ms, wall_s=wall, P=P.cpu().numpy(), N=N.cpu().numpy(), info=info)
+    del psi
+    torch.cuda.empty_cache()
+    return out
+
+
+def summarize(res, w, steps, prec_bytes):
+    M, K = w["M"], len(w["J"])
+    amp_updates = 2 * K * 2 ** M * steps
+    sec = res["ms_total"] / 1e3
+    info = res["info"]
+    launches = info["launches"]
+    state_bytes = 2 ** M * prec_bytes
+    # algorithmic bytes of one pass-kernel launch: read + write of the state
+    alg_bytes = 2 * state_bytes
+    avg_launch_s = sec / launches
+    achieved = alg_bytes / avg_launch_s / 1e9
+    return dict(value=amp_updates / sec, ms_per_step=res["ms_total"] / steps,
+                passes_per_step=info["passes_per_step"], launches=launches,
+                avg_pass_ms=avg_launch_s * 1e3, achieved_gbs=achieved,
+                hbm_gbs_per_step=launches * alg_bytes / sec / 1e9,
+                one_sweep_frac=(2 * state_bytes * steps / sec / 1e9) / HBM_PEAK_GBS)
+
+
+def cpu_baseline(w, n_couplings=4):
+    """The plain C oracle on a bounded sample of the same workload: one
+    Strang step over the first `n_couplings` couplings (2 n_couplings factor
+    applications) of the M = 30 state, complex128, all OpenMP threads."""
+    import numpy as np
+    from oracle import cref
+    cref.build(force=False)
+    M = w["M"]
+    psi = cref.init_random_phase(M, w["polarized"], w["seed"])
+    J = w["J"][:n_couplings]
+    t0 = time.perf_counter()
+    cref.trotter_run(psi, M, J, w["dt"], 1, w["observed"])
+    sec = time.perf_counter() - t0
+    del psi
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nfac = 2 * len(J)
+    return dict(value=nfac * 2 ** M / sec, unit="amplitude-updates/s", cores=threads, kind="oracle",
+                sample=f"{nfac} factor applications (one Strang step of the first {len(J)} couplings) "
+                       f"plus 2 observables on the M={M} complex128 state; {sec:.2f} s",
+                seconds=sec)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prec", default="both", choices=["c64", "c128", "both"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the state would shard over the top address bits across GPUs; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0710_3747_amd as spq
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spq.load_library()
+    w = ladder_workload()
+    steps, warmup = args.steps, args.warmup
+
+    res32 = res64 = None
+    if args.prec in ("c64", "both"):
+        print(f"[bench] complex64 path, {steps} steps", file=sys.stderr, flush=True)
+        res32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup)
+    if args.prec in ("c128", "both"):
+        print(f"[bench] complex128 path, {steps} steps", file=sys.stderr, flush=True)
+        res64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup)
+
+    head = res32 if res32 is not None else res64
+    head_bytes = 8 if res32 is not None else 16
+    s = summarize(head, w, steps, head_bytes)
+    out = {
+        "metric": METRIC,
+        "value": s["value"],
+        "unit": "amplitude-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": s["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if res32 is not None else "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "M": w["M"], "couplings": len(w["J"]),
+                   "factors_per_step": 2 * len(w["J"]), "dt": w["dt"], "seed": w["seed"],
+                   "state": "complex64" if res32 is not None else "complex128",
+                   "observable": "FP64 P and norm every step"},
+        "roofline": {"bound": "hbm", "achieved": s["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": s["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_pass", "avg_launch_ms": s["avg_pass_ms"],
+                     "launches": s["launches"]},
+        "passes_per_step": s["passes_per_step"],
+        "hbm_gbs_per_step": s["hbm_gbs_per_step"],
+        "one_sweep_frac": s["one_sweep_frac"],
+    }
+    if res32 is not None and res64 is not None:
+        s64 = summarize(res64, w, steps, 16)
+        import numpy as np
+        out["fp64"] = {"value": s64["value"], "ms_per_step": s64["ms_per_step"],
+                       "passes_per_step": s64["passes_per_step"],
+                       "achieved_gbs": s64["achieved_gbs"],
+                       "frac": s64["achieved_gbs"] / HBM_PEAK_GBS}
+        out["fp32_speedup_vs_fp64"] = s["value"] / s64["value"]
+        out["err_P_fp32_vs_fp64"] = float(np.abs(res32["P"] - res64["P"]).max())
+        out["norm_drift_fp32"] = float(np.abs(res32["N"] - 1).max())
+        out["norm_drift_fp64"] = float(np.abs(res64["N"] - 1).max())
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        cb = cpu_baseline(w)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * spin.h -- C ABI of the MI355X random-phase ensemble spin-dynamics library.
+ *
+ * The method (Alvarez, Danieli, Levstein & Pastawski, "Quantum parallelism
+ * as a tool for ensemble spin dynamics calculations", arXiv:0710.3747):
+ * instead of evolving each of the 2^(M-1) members of the infinite-
+ * temperature ensemble with site n up (Eq. (1)), evolve ONE pure state, the
+ * superposition of all members with random phases (section "Ensemble vs.
+ * pure entangled state", Eq. (2); the entangled state of section "Testing
+ * the quantum parallelism"), under a Trotter-Suzuki product of two-spin
+ * propagators, and read the local polarisation P(t) = 2 <psi(t)| I^z_n' |psi(t)>
+ * after every step.
+ *
+ * Conventions shared by every entry point:
+ *  - Sites are 0-based (the paper's site 1 is site 0).
+ *  - State layout: a contiguous vector of 2^M complex amplitudes in device
+ *    memory, interleaved (re, im); complex64 (float2) for SPIN_C64,
+ *    complex128 (double2) for SPIN_C128.  Basis index x: bit s of x is site
+ *    s; bit value 0 = spin up (I^z = +1/2).  This layout holds at every
+ *    return; internal relabelling, if any, is undone before a call returns.
+ *  - Couplings: spin_coupling {i, j, a, b} is the two-spin term of the
+ *    section "Spin systems with different coupling networks":
+ *        H_ij = a I^z_i I^z_j + (b/2)(I^+_i I^-_j + I^-_i I^+_j),  hbar = 1.
+ *    a = 0 is the XY family, b = 0 Ising, a = b isotropic, a = -2b dipolar.
+ *  - One Trotter step (the paper names the Trotter-Suzuki decomposition but
+ *    fixes no scheme; this library takes the symmetric Strang split):
+ *        exp(-i dt/2 H_0) ... exp(-i dt/2 H_{K-1}) exp(-i dt/2 H_{K-1}) ... exp(-i dt/2 H_0)
+ *    applied right-to-left, i.e. the couplings in list order, then in reverse
+ *    order.  Each factor is the exact two-spin propagator.  The library may
+ *    reorder factors with disjoint sites and merge adjacent factors on the
+ *    same pair (exact identities); the product is unchanged up to rounding.
+ *  - Observable: P[k] = sum_x (1 - 2 bit_n'(x)) |psi_x|^2 and
+ *    N[k] = sum_x |psi_x|^2 after k steps, both accumulated in FP64 whatever
+ *    the state precision; P is not divided by N.
+ *  - Ownership: the caller owns every device buffer (state, P, N); host
+ *    arrays (couplings, problem lists) are read during the call only.  The
+ *    library owns only its plan caches and workspaces (released by
+ *    spin_release_caches).  It never frees or reallocates caller memory.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is
+ *    enqueued and the call returns without synchronising; outputs are valid
+ *    once the stream has reached that point.  Argument errors are detected
+ *    on the host and returned before anything is enqueued.
+ *  - Errors: every call returns a spin_status; on failure a message is kept
+ *    in thread-local storage (spin_last_error).  No C++ exception crosses
+ *    this boundary.  Calls are thread-safe; calls that overlap on the same
+ *    state buffer race.
+ */
+#ifndef SPIN_H_
+#define SPIN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPIN_OK = 0,
+    SPIN_EINVAL = -1,        /* bad argument (range, null pointer, non-finite value) */
+    SPIN_ENOMEM = -2,        /* workspace allocation failed */
+    SPIN_EHIP = -3,          /* HIP runtime error (message in spin_last_error) */
+    SPIN_EUNSUPPORTED = -4   /* valid request this build cannot serve */
+} spin_status;
+
+typedef enum { SPIN_C64 = 1, SPIN_C128 = 2 } spin_prec;
+
+#define SPIN_MAX_M_C64 34
+#define SPIN_MAX_M_C128 33
+
+typedef struct {
+    int32_t i, j;   /* distinct sites, 0 <= i, j < M */
+    double a, b;    /* I^z I^z and flip-flop strengths (finite) */
+} spin_coupling;
+
+/*
+ * spin_init_random_phase -- write the random-phase state.
+ * Section "Ensemble vs. pure entangled state" (alpha_i = sqrt(p_i) e^{i phi_i},
+ * p_i = 1/2^(M-1), the infinite-temperature weights of section "Spin
+ * systems with different coupling networks") and the entangled state of
+ * section "Testing the quantum parallelism":
+ *   psi[x] = exp(+i phi_r) / sqrt(2^(M-1))  if bit `polarized_site` of x is 0,
+ *   psi[x] = 0                               otherwise,
+ * with r = x with bit `polarized_site` deleted, phi_r = 2 pi u(seed, r), and
+ * u(seed, r) = (z >> 11) 2^-53 where z is output r+1 of the SplitMix64
+ * stream started at state `seed` (Steele, Lea & Flood, OOPSLA 2014).
+ *   psi  : device buffer of 2^M amplitudes of `prec` (overwritten).
+ *   M    : 1..SPIN_MAX_M_C64 (c64) or 1..SPIN_MAX_M_C128 (c128).
+ * Errors: SPIN_EINVAL for a null psi, bad prec, M or site out of range.
+ */
+int spin_init_random_phase(void *psi, int32_t prec, int32_t M, int32_t polarized_site,
+                           uint64_t seed, void *stream);
+
+/*
+ * spin_trotter_evolve -- n_steps symmetric Trotter steps in place, with the
+ * observable after every step.  Trotter-Suzuki route of the introduction and
+ * summary (wave functions of size 2^M); observable of Eq. (2) with
+ * P = 2(W_11 - 1/2) (section "Testing the quantum parallelism").
+ *   psi      : device state, 2^M amplitudes of `prec` (in/out).
+ *   J, K     : host array of K >= 0 couplings (copied during the call).
+ *   dt       : time step (finite; negative runs time backwards).
+ *   n_steps  : >= 0.
+ *   observed_site : n', 0 <= n' < M.
+ *   P_dev    : device FP64 array of n_steps+1 entries; P_dev[0] is the value
+ *              at entry, P_dev[k] after k steps.  Required.
+ *   N_dev    : device FP64 array of n_steps+1 entries for the norm, or NULL.
+ * Errors: SPIN_EINVAL (null psi/P_dev, M, sites, i == j, non-finite a/b/dt,
+ * K < 0, n_steps < 0), SPIN_ENOMEM, SPIN_EHIP.
+ */
+int spin_trotter_evolve(void *psi, int32_t prec, int32_t M, const spin_coupling *J,
+                        int32_t K, double dt, int64_t n_steps, int32_t observed_site,
+                        double *P_dev, double *N_dev, void *stream);
+
+/* Execution options for spin_trotter_evolve_ex (zero-initialise = defaults). */
+typedef struct {
+    int32_t schedule;     /* 0 = fused tiles (default); 1 = one full pass per factor
+                             (the plain, unfused schedule, kept as a cross-check) */
+    int32_t tile_bits;    /* k of the 2^k-amplitude tiles; 0 = autotuned / default */
+    int32_t reg_bits;     /* amplitudes per lane = 2^reg_bits; 0 = default */
+    int32_t coalesce_bits;/* low address bits every tile keeps; 0 = default */
+    int32_t engine;       /* 0 = VALU butterflies (default); 1 = FP32 MFMA block stages */
+    int32_t no_merge;     /* 1 = do not merge adjacent same-pair factors */
+    int32_t use_graph;    /* 1 = launch through a captured hipGraph */
+    int32_t reserved[9];
+} spin_options;
+
+/* As spin_trotter_evolve with explicit options (NULL = defaults). */
+int spin_trotter_evolve_ex(void *psi, int32_t prec, int32_t M, const spin_coupling *J,
+                           int32_t K, double dt, int64_t n_steps, int32_t observed_site,
+                           double *P_dev, double *N_dev, const spin_options *opt,
+                           void *stream);
+
+/*
+ * spin_local_polarization -- P = sum_x (1 - 2 bit_site(x)) |psi_x|^2 and the
+ * norm, FP64, of the state as it is (Eq. (2), P = 2(W - 1/2)).
+ *   out_dev : device FP64 array of 2 entries: out_dev[0] = P, out_dev[1] = N.
+ * Errors: SPIN_EINVAL (null pointers, prec, M, site), SPIN_ENOMEM, SPIN_EHIP.
+ */
+int spin_local_polarization(const void *psi, int32_t prec, int32_t M, int32_t site,
+                            double *out_dev, void *stream);
+
+/*
+ * Batched evolution of independent problems of uneven size (disorder
+ * realisations, or independent phase draws whose mean is Eq. (4)), in ONE
+ * persistent launch.  Every problem uses the same prec, dt and n_steps.
+ */
+typedef struct {
+    void *psi;               /* device state of this problem, 2^M amplitudes */
+    int32_t M, K;            /* size and number of couplings */
+    int64_t coupling_offset; /* index of its first coupling in J_all */
+    int32_t polarized_site;  /* used when init_random_phase != 0 */
+    int32_t observed_site;
+    uint64_t seed;           /* phase seed when init_random_phase != 0 */
+    double *P_dev;           /* n_steps+1 FP64 entries (required) */
+    double *N_dev;           /* n_steps+1 FP64 entries or NULL */
+} spin_problem;
+
+/*
+ * spin_trotter_evolve_batch -- for every problem, optionally write its
+ * random-phase state (as spin_init_random_phase), then evolve it n_steps
+ * steps (as spin_trotter_evolve) writing its P and N.
+ *   probs, n       : host array of n >= 0 problems (read during the call).
+ *   J_all, K_total : host array holding every problem's couplings.
+ *   init_random_phase : 1 = initialise each state inside the launch first.
+ * The states must not overlap.  Errors as spin_trotter_evolve, reported for
+ * the first offending problem.
+ */
+int spin_trotter_evolve_batch(const spin_problem *probs, int32_t n, const spin_coupling *J_all,
+                              int64_t K_total, int32_t prec, double dt, int64_t n_steps,
+                              int32_t init_random_phase, void *stream);
+
+/*
+ * Introspection of the execution plan (host only: no device work, usable
+ * without a GPU).  The plan is what spin_trotter_evolve_ex would run for the
+ * same arguments.
+ */
+typedef struct {
+    int32_t path;           /* 0 = one pass per factor, 1 = whole state in one workgroup,
+                               2 = tiled passes */
+    int32_t tile_bits;      /* k (path 2), M (path 1) */
+    int32_t reg_bits;       /* amplitudes per lane = 2^reg_bits */
+    int32_t lanes;          /* lanes per workgroup */
+    int32_t coalesce_bits;  /* low address bits in every tile (path 2) */
+    int32_t templates;      /* distinct pass templates (path 2) */
+    int32_t period_steps, period_passes;  /* repeating block of the plan (path 2) */
+    int32_t stages_total;   /* register stages over all templates */
+    int32_t reserved_;
+    int64_t launches;       /* pass-kernel launches for the whole call */
+    int64_t factor_ops;     /* two-spin factor applications after merging, whole call */
+    double passes_per_step; /* launches / n_steps (path 2) */
+} spin_plan_info;
+
+int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
+                       int64_t n_steps, int32_t observed_site, const spin_options *opt,
+                       spin_plan_info *info);
+
+/*
+ * spin_plan_trace -- the op sequence the plan applies, in execution order,
+ * as records of 5 doubles: a factor exp(-i(A I^z_i I^z_j + (B/2)(I^+_i I^-_j +
+ * I^-_i I^+_j))) is (0, i, j, A, B) (A, B = strengths times time, merged
+ * factors summed); an observable of step k is (1, k, 0, 0, 0).
+ *   buf, cap : host buffer of cap records (may be NULL with cap = 0).
+ *   len      : number of records of the full trace (always written).
+ * Returns SPIN_OK even when cap < *len (the buffer then holds a prefix).
+ * Host only; no device work.
+ */
+int spin_plan_trace(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
+                    int64_t n_steps, int32_t observed_site, const spin_options *opt,
+                    double *buf, int64_t cap, int64_t *len);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *spin_last_error(void);
+
+/* Frees plan caches, captured graphs and workspaces.  Not concurrent-safe
+ * with in-flight calls; synchronise the streams used first. */
+void spin_release_caches(void);
+
+/* Library version string. */
+const char *spin_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIN_H_ */

@@ -1,0 +1,619 @@
+// abi.cpp -- the C ABI of include/spin.h: argument validation, plan caches,
+// workspaces and launch orchestration.  Every step of the path runs in the
+// kernels of kernels.hip; this file only plans and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/spin.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+#include "abi_internal.hpp"
+
+namespace spinqp {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SPIN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+// ------------------------------------------------------------- validation
+int validate_common(const void* psi, int32_t prec, int32_t M) {
+    if (!psi) return fail(SPIN_EINVAL, "psi is NULL");
+    if (prec != SPIN_C64 && prec != SPIN_C128) return fail(SPIN_EINVAL, "prec must be SPIN_C64 or SPIN_C128");
+    const int maxM = prec == SPIN_C64 ? SPIN_MAX_M_C64 : SPIN_MAX_M_C128;
+    if (M < 1 || M > maxM) {
+        std::ostringstream os;
+        os << "M = " << M << " out of range 1.." << maxM;
+        return fail(SPIN_EINVAL, os.str());
+    }
+    if (reinterpret_cast<uintptr_t>(psi) % 16 != 0) return fail(SPIN_EINVAL, "psi must be 16-byte aligned");
+    return SPIN_OK;
+}
+
+int validate_couplings(int32_t M, const spin_coupling* J, int64_t K, std::vector<Coupling>* out) {
+    if (K < 0) return fail(SPIN_EINVAL, "K < 0");
+    if (K > 0 && !J) return fail(SPIN_EINVAL, "J is NULL with K > 0");
+    out->clear();
+    out->reserve(size_t(K));
+    for (int64_t g = 0; g < K; ++g) {
+        const spin_coupling& c = J[g];
+        std::ostringstream os;
+        if (c.i < 0 || c.i >= M || c.j < 0 || c.j >= M) {
+            os << "coupling " << g << ": site out of range 0.." << M - 1;
+            return fail(SPIN_EINVAL, os.str());
+        }
+        if (c.i == c.j) {
+            os << "coupling " << g << ": i == j";
+            return fail(SPIN_EINVAL, os.str());
+        }
+        if (!std::isfinite(c.a) || !std::isfinite(c.b)) {
+            os << "coupling " << g << ": non-finite a or b";
+            return fail(SPIN_EINVAL, os.str());
+        }
+        out->push_back(Coupling{c.i, c.j, c.a, c.b});
+    }
+    return SPIN_OK;
+}
+
+// ------------------------------------------------------------ workspaces
+// Device scratch for per-workgroup partial sums, grow-only, one per
+// (device, stream): calls on different streams never share one.
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_mu;
+static std::map<std::pair<int, hipStream_t>, Scratch> g_scratch;
+
+int scratch_get(hipStream_t st, size_t bytes, void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch& s = g_scratch[{dev, st}];
+    if (s.bytes < bytes) {
+        if (s.ptr) {
+            // previous work on this stream may still read it
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipFree(s.ptr));
+            s.ptr = nullptr;
+            s.bytes = 0;
+        }
+        size_t want = std::max(bytes, size_t(1) << 20);
+        if (hipMalloc(&s.ptr, want) != hipSuccess) {
+            s.ptr = nullptr;
+            return fail(SPIN_ENOMEM, "workspace allocation failed");
+        }
+        s.bytes = want;
+    }
+    *out = s.ptr;
+    return SPIN_OK;
+}
+
+// ------------------------------------------------------------- plan cache
+struct PlanKey {
+    int dev, prec, M, observed, k, r, nt, c, merge;
+    double dt;
+    int64_t n_steps;
+    std::vector<double> J;    // flattened couplings
+    bool operator<(const PlanKey& o) const {
+        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, dt, n_steps, J) <
+               std::tie(o.dev, o.prec, o.M, o.observed, o.k, o.r, o.nt, o.c, o.merge, o.dt,
+                        o.n_steps, o.J);
+    }
+};
+
+struct DevicePlan {
+    bool resident = false;
+    StreamPlan sp;
+    PassShape shape{};
+    int k = 0, nwg = 0;
+    int64_t tiles_per_wg = 0;
+    // device tables
+    void* d_passes = nullptr;
+    void* d_stages = nullptr;
+    void* d_ops = nullptr;
+    // resident
+    int res_r = 0, res_nt = 0;
+    int pro_stage0 = 0, pro_nstage = 0, step_stage0 = 0, step_nstage = 0;
+    // per template: measurement steps (relative)
+    std::vector<std::vector<int64_t>> meas;
+    size_t stages_total = 0;
+    ~DevicePlan() {
+        if (d_passes) (void)hipFree(d_passes);
+        if (d_stages) (void)hipFree(d_stages);
+        if (d_ops) (void)hipFree(d_ops);
+    }
+};
+
+static std::map<PlanKey, std::shared_ptr<DevicePlan>> g_plans;
+
+template <typename T>
+static int upload_tables(const DevTables<T>& tb, DevicePlan* dp) {
+    auto up = [&](const void* src, size_t n, void** dst) -> int {
+        if (n == 0) n = 16;
+        if (hipMalloc(dst, n) != hipSuccess) return fail(SPIN_ENOMEM, "plan table allocation failed");
+        if (src) HIP_TRY(hipMemcpy(*dst, src, n, hipMemcpyHostToDevice));
+        return SPIN_OK;
+    };
+    int rc;
+    if ((rc = up(tb.passes.data(), tb.passes.size() * sizeof(DevPass), &dp->d_passes))) return rc;
+    if ((rc = up(tb.stages.data(), tb.stages.size() * sizeof(DevStage), &dp->d_stages))) return rc;
+    if ((rc = up(tb.ops.data(), tb.ops.size() * sizeof(DevOp<T>), &dp->d_ops))) return rc;
+    return SPIN_OK;
+}
+
+// Launch shapes the pass kernel is instantiated for: (register bits, lanes).
+static bool shape_exists(bool f32, int r, int nt) {
+    if (f32) return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 5 && nt == 512) ||
+                    (r == 6 && nt == 256);
+    return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 4 && nt == 512);
+}
+
+// Launch shape: tile bits k = r + log2(nt).  Defaults: complex64 tiles of
+// 2^14 amplitudes (128 KiB of LDS), complex128 tiles of 2^13 (128 KiB).
+Shape choose_shape(int prec, int M, const spin_options* opt) {
+    Shape s;
+    const bool f32 = prec == SPIN_C64;
+    int k = f32 ? 14 : 13;
+    s.r = f32 ? 5 : 4;
+    s.c = 3;
+    if (opt && opt->tile_bits > 0) {
+        k = opt->tile_bits;
+        s.r = f32 ? (k <= 12 ? 4 : 5) : 4;
+    }
+    if (opt && opt->reg_bits > 0) s.r = opt->reg_bits;
+    if (opt && opt->coalesce_bits > 0) s.c = opt->coalesce_bits;
+    if (f32 && s.c < 1) s.c = 1;     // two-amplitude vector accesses need bit 0
+    s.nt = (k - s.r >= 0 && k - s.r < 16) ? (1 << (k - s.r)) : 0;
+    s.k = k;
+    s.valid = shape_exists(f32, s.r, s.nt);
+    s.res_cap = f32 ? 14 : 13;
+    s.resident = M <= s.res_cap;
+    return s;
+}
+
+static int res_shape(int prec, int M, int* r, int* nt) {
+    const int rmax = prec == SPIN_C64 ? 5 : 4;
+    *r = std::min(rmax, M);
+    const int tb = M - *r;    // thread bits
+    if (tb <= 6) *nt = 64;
+    else if (tb <= 8) *nt = 256;
+    else *nt = 512;
+    return SPIN_OK;
+}
+
+template <typename T>
+static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const Shape& sh,
+                      std::shared_ptr<DevicePlan>* out) {
+    auto dp = std::make_shared<DevicePlan>();
+    DevTables<T> tb;
+    try {
+        if (sh.resident) {
+            dp->resident = true;
+            res_shape(key.prec, key.M, &dp->res_r, &dp->res_nt);
+            ResidentPlan rp = plan_resident(key.M, J, key.dt, key.observed, key.merge != 0, dp->res_r);
+            const int nthreads = 1 << std::max(0, key.M - dp->res_r);
+            dp->pro_stage0 = 0;
+            encode_pass<T>(rp.prologue, key.M, key.observed, dp->res_r, nthreads, 1, tb);
+            dp->pro_nstage = int(tb.stages.size());
+            dp->step_stage0 = int(tb.stages.size());
+            encode_pass<T>(rp.step, key.M, key.observed, dp->res_r, nthreads, 1, tb);
+            dp->step_nstage = int(tb.stages.size()) - dp->step_stage0;
+            dp->stages_total = tb.stages.size();
+        } else {
+            PassParams pp;
+            pp.k = sh.k;
+            pp.r = sh.r;
+            pp.c = sh.c;
+            dp->sp = plan_stream(key.M, J, key.dt, key.n_steps, key.observed, key.merge != 0, pp);
+            dp->shape = PassShape{sh.r, sh.nt};
+            dp->k = sh.k;
+            const int64_t ntiles = int64_t(1) << (key.M - sh.k);
+            int dev_cu = 256;
+            {
+                hipDeviceProp_t prop;
+                if (hipGetDeviceProperties(&prop, key.dev) == hipSuccess) dev_cu = prop.multiProcessorCount;
+            }
+            // persistent grid: a power of two <= tiles, ~4 workgroups per CU
+            int64_t nwg = 1;
+            while (nwg * 2 <= ntiles && nwg * 2 <= int64_t(dev_cu) * 4) nwg *= 2;
+            dp->nwg = int(nwg);
+            dp->tiles_per_wg = ntiles / nwg;
+            const int vec = sizeof(T) == 4 ? 2 : 1;
+            for (const HostPass& hp : dp->sp.passes) {
+                encode_pass<T>(hp, key.M, key.observed, sh.r, sh.nt, vec, tb);
+                std::vector<int64_t> ms;
+                for (const Op& op : hp.ops)
+                    if (op.kind == 1) ms.push_back(op.step);
+                dp->meas.push_back(ms);
+            }
+            dp->stages_total = tb.stages.size();
+        }
+    } catch (const std::exception& e) {
+        return fail(SPIN_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+    }
+    int rc = upload_tables<T>(tb, dp.get());
+    if (rc) return rc;
+    *out = dp;
+    return SPIN_OK;
+}
+
+int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
+             int observed, const spin_options* opt, std::shared_ptr<DevicePlan>* out,
+             Shape* shape_out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    Shape sh = choose_shape(prec, M, opt);
+    if (!sh.resident && !sh.valid) {
+        std::ostringstream os;
+        os << "no pass kernel for tile_bits " << sh.k << " with reg_bits " << sh.r;
+        return fail(SPIN_EUNSUPPORTED, os.str());
+    }
+    PlanKey key{dev, prec, M, observed, sh.k, sh.r, sh.nt, sh.c,
+                (opt && opt->no_merge) ? 0 : 1, dt, sh.resident ? 0 : n_steps, {}};
+    key.J.reserve(J.size() * 4);
+    for (const Coupling& c : J) {
+        key.J.push_back(c.i);
+        key.J.push_back(c.j);
+        key.J.push_back(c.a);
+        key.J.push_back(c.b);
+    }
+    if (shape_out) *shape_out = sh;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) {
+            *out = it->second;
+            return SPIN_OK;
+        }
+    }
+    std::shared_ptr<DevicePlan> dp;
+    int rc = prec == SPIN_C64 ? build_plan<float>(key, J, sh, &dp) : build_plan<double>(key, J, sh, &dp);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans[key] = dp;
+    *out = dp;
+    return SPIN_OK;
+}
+
+// ------------------------------------------------------------- evolve
+template <typename T>
+static int evolve_naive(void* psi, int M, const std::vector<Coupling>& J, double dt,
+                        int64_t n_steps, int observed, double* P, double* N, hipStream_t st) {
+    const int nblk = 1024;
+    void* scratch = nullptr;
+    int rc = scratch_get(st, size_t(nblk) * 2 * sizeof(double), &scratch);
+    if (rc) return rc;
+    double* part = static_cast<double*>(scratch);
+    auto observe = [&](int64_t k) -> int {
+        HIP_TRY((launch_observe<T>(psi, M, observed, part, nblk, st)));
+        HIP_TRY(launch_reduce(part, nblk, 1, 0, 1, P + k, N ? N + k : nullptr, st));
+        return SPIN_OK;
+    };
+    if ((rc = observe(0))) return rc;
+    const double tau = 0.5 * dt;
+    for (int64_t k = 1; k <= n_steps; ++k) {
+        for (int dir = 0; dir < 2; ++dir) {
+            for (size_t n = 0; n < J.size(); ++n) {
+                const Coupling& c = dir == 0 ? J[n] : J[J.size() - 1 - n];
+                const double th = 0.5 * c.b * tau;
+                int pieces = 1;
+                while (std::fabs(th / pieces) > 1.5707963267948966) pieces *= 2;
+                for (int pc = 0; pc < pieces; ++pc) {
+                    const double t = th / pieces;
+                    const double A = pc == 0 ? c.a * tau : 0.0;
+                    HIP_TRY((launch_factor<T>(psi, M, std::min(c.i, c.j), std::max(c.i, c.j),
+                                              std::tan(0.5 * t), std::sin(t), std::cos(0.25 * A),
+                                              std::sin(0.25 * A), A != 0.0 ? 1 : 0, st)));
+                }
+            }
+        }
+        if ((rc = observe(k))) return rc;
+    }
+    return SPIN_OK;
+}
+
+template <typename T>
+static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double dt,
+                        int64_t n_steps, int observed, double* P, double* N,
+                        const spin_options* opt, hipStream_t st) {
+    std::shared_ptr<DevicePlan> dp;
+    Shape sh;
+    int rc = get_plan(sizeof(T) == 4 ? SPIN_C64 : SPIN_C128, M, J, dt, n_steps, observed, opt, &dp, &sh);
+    if (rc) return rc;
+    if (dp->resident) {
+        ResidentJob job{};
+        job.psi = psi;
+        job.P = P;
+        job.N = N;
+        job.M = M;
+        job.init = 0;
+        job.pro_stage0 = dp->pro_stage0;
+        job.pro_nstage = dp->pro_nstage;
+        job.step_stage0 = dp->step_stage0;
+        job.step_nstage = dp->step_nstage;
+        HIP_TRY((launch_resident<T>(dp->res_r, dp->res_nt, job, nullptr, 1,
+                                    static_cast<const DevStage*>(dp->d_stages),
+                                    static_cast<const DevOp<T>*>(dp->d_ops), n_steps, st)));
+        return SPIN_OK;
+    }
+    const int64_t total = n_steps + 1;
+    const int ch = int(std::min<int64_t>(total, 1024));
+    void* scratch = nullptr;
+    rc = scratch_get(st, size_t(ch) * dp->nwg * 2 * sizeof(double), &scratch);
+    if (rc) return rc;
+    double* part = static_cast<double*>(scratch);
+    int64_t measured = 0, reduced = 0;
+    const size_t nl = dp->sp.launch_tmpl.size();
+    for (size_t l = 0; l < nl; ++l) {
+        const int t = dp->sp.launch_tmpl[l];
+        const int64_t off = dp->sp.launch_offset[l];
+        HIP_TRY((launch_pass<T>(dp->shape, psi, static_cast<const DevPass*>(dp->d_passes),
+                                static_cast<const DevStage*>(dp->d_stages),
+                                static_cast<const DevOp<T>*>(dp->d_ops), t, dp->tiles_per_wg,
+                                dp->nwg, part, off, ch, st)));
+        for (int64_t s : dp->meas[t]) measured = std::max(measured, s + off + 1);
+        if (measured - reduced >= ch / 2 || (l + 1 == nl && measured > reduced)) {
+            HIP_TRY(launch_reduce(part, dp->nwg, ch, reduced, measured - reduced, P, N, st));
+            reduced = measured;
+        }
+    }
+    if (reduced != total) {
+        std::ostringstream os;
+        os << "internal: plan measured " << reduced << " of " << total << " steps";
+        return fail(SPIN_EUNSUPPORTED, os.str());
+    }
+    return SPIN_OK;
+}
+
+}  // namespace spinqp
+
+using namespace spinqp;
+
+extern "C" {
+
+const char* spin_last_error(void) { return g_err.c_str(); }
+
+const char* spin_version(void) { return "spinqp 0.1 (gfx950)"; }
+
+int spin_init_random_phase(void* psi, int32_t prec, int32_t M, int32_t polarized_site,
+                           uint64_t seed, void* stream) {
+    int rc = validate_common(psi, prec, M);
+    if (rc) return rc;
+    if (polarized_site < 0 || polarized_site >= M) return fail(SPIN_EINVAL, "polarized_site out of range");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = prec == SPIN_C64 ? launch_init<float>(psi, M, polarized_site, seed, st)
+                                    : launch_init<double>(psi, M, polarized_site, seed, st);
+    if (e != hipSuccess) return fail(SPIN_EHIP, std::string("init launch: ") + hipGetErrorString(e));
+    g_err.clear();
+    return SPIN_OK;
+}
+
+int spin_local_polarization(const void* psi, int32_t prec, int32_t M, int32_t site,
+                            double* out_dev, void* stream) {
+    int rc = validate_common(psi, prec, M);
+    if (rc) return rc;
+    if (site < 0 || site >= M) return fail(SPIN_EINVAL, "site out of range");
+    if (!out_dev) return fail(SPIN_EINVAL, "out_dev is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nblk = 1024;
+    void* scratch = nullptr;
+    if ((rc = scratch_get(st, size_t(nblk) * 2 * sizeof(double), &scratch))) return rc;
+    double* part = static_cast<double*>(scratch);
+    hipError_t e = prec == SPIN_C64 ? launch_observe<float>(psi, M, site, part, nblk, st)
+                                    : launch_observe<double>(psi, M, site, part, nblk, st);
+    if (e == hipSuccess) e = launch_reduce(part, nblk, 1, 0, 1, out_dev, out_dev + 1, st);
+    if (e != hipSuccess) return fail(SPIN_EHIP, std::string("observe launch: ") + hipGetErrorString(e));
+    g_err.clear();
+    return SPIN_OK;
+}
+
+int spin_trotter_evolve_ex(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                           double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
+                           double* N_dev, const spin_options* opt, void* stream) {
+    try {
+        int rc = validate_common(psi, prec, M);
+        if (rc) return rc;
+        if (!P_dev) return fail(SPIN_EINVAL, "P_dev is NULL");
+        if (!std::isfinite(dt)) return fail(SPIN_EINVAL, "dt is not finite");
+        if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
+        if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
+        if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
+        if (opt && opt->engine != 0) return fail(SPIN_EUNSUPPORTED, "engine option not available");
+        std::vector<Coupling> Jv;
+        if ((rc = validate_couplings(M, J, K, &Jv))) return rc;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const bool naive = opt && opt->schedule == 1;
+        if (naive) {
+            rc = prec == SPIN_C64 ? evolve_naive<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, st)
+                                  : evolve_naive<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, st);
+        } else {
+            rc = prec == SPIN_C64
+                     ? evolve_fused<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, st)
+                     : evolve_fused<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, st);
+        }
+        if (rc == SPIN_OK) g_err.clear();
+        return rc;
+    } catch (const std::exception& e) {
+        return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());
+    }
+}
+
+int spin_trotter_evolve(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                        double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
+                        double* N_dev, void* stream) {
+    return spin_trotter_evolve_ex(psi, prec, M, J, K, dt, n_steps, observed_site, P_dev, N_dev,
+                                  nullptr, stream);
+}
+
+void spin_release_caches(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.clear();
+    for (auto& kv : g_scratch)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    g_scratch.clear();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- introspection
+namespace {
+
+int host_args(int32_t prec, int32_t M, const spin_coupling* J, int32_t K, double dt,
+              int64_t n_steps, int32_t observed, std::vector<Coupling>* Jv) {
+    if (prec != SPIN_C64 && prec != SPIN_C128) return fail(SPIN_EINVAL, "bad prec");
+    const int maxM = prec == SPIN_C64 ? SPIN_MAX_M_C64 : SPIN_MAX_M_C128;
+    if (M < 1 || M > maxM) return fail(SPIN_EINVAL, "M out of range");
+    if (!std::isfinite(dt)) return fail(SPIN_EINVAL, "dt is not finite");
+    if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
+    if (observed < 0 || observed >= M) return fail(SPIN_EINVAL, "observed_site out of range");
+    return validate_couplings(M, J, K, Jv);
+}
+
+struct HostPlan {
+    int path = 2;
+    Shape sh;
+    StreamPlan sp;
+    ResidentPlan rp;
+    int res_r = 0, res_nt = 0;
+};
+
+int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double dt, int64_t n_steps,
+              int32_t observed, const spin_options* opt, HostPlan* hp) {
+    hp->sh = choose_shape(prec, M, opt);
+    if (!(opt && opt->schedule == 1) && !hp->sh.resident && !hp->sh.valid)
+        return fail(SPIN_EUNSUPPORTED, "no pass kernel for the requested tile shape");
+    const bool merge = !(opt && opt->no_merge);
+    try {
+        if (opt && opt->schedule == 1) {
+            hp->path = 0;
+        } else if (hp->sh.resident) {
+            hp->path = 1;
+            const int rmax = prec == SPIN_C64 ? 5 : 4;
+            hp->res_r = std::min(rmax, int(M));
+            hp->rp = plan_resident(M, Jv, dt, observed, merge, hp->res_r);
+        } else {
+            hp->path = 2;
+            PassParams pp;
+            pp.k = hp->sh.k;
+            pp.r = hp->sh.r;
+            pp.c = hp->sh.c;
+            hp->sp = plan_stream(M, Jv, dt, n_steps, observed, merge, pp);
+        }
+    } catch (const std::exception& e) {
+        return fail(SPIN_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+    }
+    return SPIN_OK;
+}
+
+}  // namespace
+
+extern "C" int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                                  double dt, int64_t n_steps, int32_t observed_site,
+                                  const spin_options* opt, spin_plan_info* info) {
+    if (!info) return fail(SPIN_EINVAL, "info is NULL");
+    std::vector<Coupling> Jv;
+    int rc = host_args(prec, M, J, K, dt, n_steps, observed_site, &Jv);
+    if (rc) return rc;
+    HostPlan hp;
+    if ((rc = host_plan(prec, M, Jv, dt, n_steps, observed_site, opt, &hp))) return rc;
+    std::memset(info, 0, sizeof(*info));
+    info->path = hp.path;
+    if (hp.path == 0) {
+        info->launches = n_steps * int64_t(2 * Jv.size());
+        info->factor_ops = info->launches;
+        info->passes_per_step = 2.0 * Jv.size();
+    } else if (hp.path == 1) {
+        info->tile_bits = M;
+        info->reg_bits = hp.res_r;
+        info->launches = 1;
+        info->stages_total = int(hp.rp.prologue.stages.size() + hp.rp.step.stages.size());
+        int64_t f = 0;
+        for (const Op& op : hp.rp.step.ops) f += op.kind == 0;
+        info->factor_ops = f * n_steps;
+    } else {
+        info->tile_bits = hp.sh.k;
+        info->reg_bits = hp.sh.r;
+        info->lanes = hp.sh.nt;
+        info->coalesce_bits = hp.sh.c;
+        info->templates = int(hp.sp.passes.size());
+        info->period_steps = hp.sp.period_steps;
+        info->period_passes = hp.sp.period_passes;
+        int64_t st = 0;
+        for (auto& p : hp.sp.passes) st += int64_t(p.stages.size());
+        info->stages_total = int(st);
+        info->launches = int64_t(hp.sp.launch_tmpl.size());
+        int64_t f = 0;
+        for (int t : hp.sp.launch_tmpl)
+            for (const Op& op : hp.sp.passes[t].ops) f += op.kind == 0;
+        info->factor_ops = f;
+        info->passes_per_step = hp.sp.passes_per_step();
+    }
+    g_err.clear();
+    return SPIN_OK;
+}
+
+extern "C" int spin_plan_trace(int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                               double dt, int64_t n_steps, int32_t observed_site,
+                               const spin_options* opt, double* buf, int64_t cap, int64_t* len) {
+    if (!len) return fail(SPIN_EINVAL, "len is NULL");
+    if (cap > 0 && !buf) return fail(SPIN_EINVAL, "buf is NULL with cap > 0");
+    std::vector<Coupling> Jv;
+    int rc = host_args(prec, M, J, K, dt, n_steps, observed_site, &Jv);
+    if (rc) return rc;
+    HostPlan hp;
+    if ((rc = host_plan(prec, M, Jv, dt, n_steps, observed_site, opt, &hp))) return rc;
+    int64_t n = 0;
+    auto put = [&](double a, double b, double c, double d, double e) {
+        if (n < cap) {
+            double* r = buf + 5 * n;
+            r[0] = a; r[1] = b; r[2] = c; r[3] = d; r[4] = e;
+        }
+        ++n;
+    };
+    auto put_pass = [&](const HostPass& p, int64_t off) {
+        for (const HostStage& s : p.stages)
+            for (int o : s.ops) {
+                const Op& op = p.ops[o];
+                if (op.kind == 1) put(1, double(op.step + off), 0, 0, 0);
+                else put(0, op.i, op.j, op.A, op.B);
+            }
+    };
+    if (hp.path == 0) {
+        const double tau = 0.5 * dt;
+        put(1, 0, 0, 0, 0);
+        for (int64_t k = 1; k <= n_steps; ++k) {
+            for (size_t g = 0; g < Jv.size(); ++g) put(0, Jv[g].i, Jv[g].j, Jv[g].a * tau, Jv[g].b * tau);
+            for (size_t g = Jv.size(); g-- > 0;) put(0, Jv[g].i, Jv[g].j, Jv[g].a * tau, Jv[g].b * tau);
+            put(1, double(k), 0, 0, 0);
+        }
+    } else if (hp.path == 1) {
+        put_pass(hp.rp.prologue, 0);
+        for (int64_t k = 1; k <= n_steps; ++k) put_pass(hp.rp.step, k - 1);
+    } else {
+        for (size_t l = 0; l < hp.sp.launch_tmpl.size(); ++l)
+            put_pass(hp.sp.passes[hp.sp.launch_tmpl[l]], hp.sp.launch_offset[l]);
+    }
+    *len = n;
+    g_err.clear();
+    return SPIN_OK;
+}

@@ -1,0 +1,79 @@
+// device_plan.hpp -- plain-old-data plan records shared by the host planner
+// and the gfx950 kernels, plus the LDS address swizzle both sides use.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define SPIN_HD __host__ __device__
+#else
+#define SPIN_HD
+#endif
+
+namespace spinqp {
+
+constexpr int kMaxTileBits = 14;    // 2^14 amplitudes: 128 KiB of complex64 in LDS
+constexpr int kMaxRegBits = 6;      // at most 64 amplitudes per lane
+constexpr int kMaxMeas = 4;         // observable slots one pass can hold
+constexpr int kMaxSites = 40;
+
+// Op codes.  A two-spin factor on register bits (qa < qb) of a stage has
+// code qa*8 + qb; kOpZZ is or-ed in when the factor carries an I^z I^z
+// phase.  kOpMeas accumulates the observable of the state at that point.
+constexpr int32_t kOpZZ = 64;
+constexpr int32_t kOpMeas = 255;
+
+// One op of a stage.  For a factor with integrated strengths
+// (A, B) = (sum a*tau, sum b*tau) over the merged two-spin propagators:
+//   theta = B/2, t = tan(theta/2), s = sin(theta)     (three-shear rotation)
+//   (pr, pi) = exp(+i A/4)                             (anti-aligned phase)
+// For kOpMeas, aux is the measurement slot of the pass (resident kernels:
+// unused).
+template <typename T>
+struct DevOp {
+    int32_t code;
+    int32_t aux;
+    T t, s, pr, pi;
+};
+
+// One stage: the amplitudes of a tile are gathered from LDS into registers
+// with register bit q <-> tile-local position rpos[q], the stage's ops run
+// on registers, and the registers are scattered back.
+struct DevStage {
+    int32_t op0, nop;         // op range
+    int32_t ntb;              // number of thread bits (tile bits - register bits)
+    int32_t obs_tq;           // thread bit holding the observed site, or -1
+    int32_t obs_mask;         // register-index mask of the observed site (0 if none)
+    int32_t pad_;
+    int8_t tpos[16];          // tile-local position of thread bit q
+    uint32_t soff[64];        // swizzled LDS offset of register j (bits rpos)
+};
+
+// One tiled pass over the whole state.
+struct DevPass {
+    int32_t k;                // tile bits
+    int32_t stage0, nstage;   // stage range
+    int32_t writes;           // 0: read-only pass (observable only)
+    int32_t nfree;            // number of non-tile bits
+    int32_t obs_free_bit;     // global bit of the observed site if it is not a tile bit, else -1
+    int32_t nmeas;            // measurements in this pass
+    int32_t pad_;
+    int64_t meas_step[kMaxMeas];   // step label of measurement slot m (plus launch offset)
+    int8_t tbit[16];          // global bit of tile-local position p
+    int8_t fbit[kMaxSites];   // global bits not in the tile, increasing
+    int64_t iter_goff[64];    // global element offset of load/store iteration it
+    uint32_t iter_soff[64];   // swizzled LDS offset of load/store iteration it
+};
+
+// LDS swizzle: xor a band of higher local-index bits into the lowest bits
+// so that lanes striding by a power of two spread over the banks.  It is
+// linear over GF(2): swz(a ^ b) = swz(a) ^ swz(b).
+template <int ElemBytes>
+SPIN_HD inline uint32_t lds_swizzle(uint32_t l) {
+    // 8-byte elements: 32 per 256-byte bank row; 16-byte elements: 16.
+    constexpr uint32_t shift = ElemBytes == 8 ? 5 : 4;
+    constexpr uint32_t mask = ElemBytes == 8 ? 31 : 15;
+    return l ^ ((l >> shift) & mask);
+}
+
+}  // namespace spinqp

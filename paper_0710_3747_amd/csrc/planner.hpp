@@ -1,0 +1,121 @@
+// planner.hpp -- host-side planning of the Strang product into tiled passes.
+//
+// The symmetric Trotter step (couplings in list order with tau = dt/2, then
+// in reverse order with tau = dt/2) is expanded into an op sequence with an
+// observable op after every step.  Adjacent factors on the same pair with
+// no op in between touching either site are merged (exact: the two-spin
+// propagators of one pair commute and add their strengths).  The sequence is
+// then cut into passes: each pass owns a set of k sites (its tile bits) and
+// applies a down-set-closed run of ops whose sites all lie in that set, so
+// every pass is one read + write sweep of the state.  Inside a pass, ops are
+// grouped into stages whose sites fit the r register bits of a lane.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "device_plan.hpp"
+
+namespace spinqp {
+
+struct Coupling {
+    int i, j;
+    double a, b;
+};
+
+struct Op {
+    int kind;          // 0 = factor, 1 = observable
+    int i, j;          // factor sites (i < j); observable: i = j = observed site
+    double A, B;       // integrated strengths sum(a*tau), sum(b*tau)
+    int64_t step;      // observable: its step index; factor: step of first occurrence
+    int idx;           // emission index inside that step (identity for period search)
+};
+
+// Emits the merged op sequence step by step.
+class SeqBuilder {
+  public:
+    SeqBuilder(int M, const std::vector<Coupling>& J, double dt, int observed, bool merge);
+    void emit_observable(int64_t step);
+    void emit_step(int64_t step);   // forward + reverse factors, then observable(step)
+    std::vector<Op> ops;
+
+  private:
+    void emit_factor(const Coupling& c, double tau, int64_t step);
+    int observed_;
+    bool merge_;
+    double dt_;
+    std::vector<Coupling> J_;
+    std::vector<int> last_;    // per site: index of the last op touching it, or -1
+    int idx_ = 0;
+    int64_t cur_step_ = -1;
+};
+
+struct HostStage {
+    std::vector<int> regs;     // register bit q -> tile-local position
+    std::vector<int> ops;      // indices into HostPass::ops
+};
+
+struct HostPass {
+    std::vector<int> sites;    // tile-local position p -> site (= global bit)
+    std::vector<Op> ops;       // execution order
+    std::vector<HostStage> stages;
+    bool writes = true;
+};
+
+struct PassParams {
+    int k = 14;                // tile bits
+    int r = 5;                 // register bits
+    int c = 4;                 // low global bits every tile must contain
+    int max_meas = kMaxMeas;
+};
+
+// Plan of one evolve call on the tiled (streaming) path.  Launch l runs
+// pass template tmpl[l] with its observable step labels shifted by
+// offset[l].
+struct StreamPlan {
+    std::vector<HostPass> passes;      // templates
+    std::vector<int> launch_tmpl;
+    std::vector<int64_t> launch_offset;
+    int64_t n_steps = 0;
+    int period_steps = 0;              // 0 if no period was used
+    int period_passes = 0;
+    double passes_per_step() const {
+        return n_steps ? double(launch_tmpl.size()) / double(n_steps) : 0.0;
+    }
+};
+
+// Stages for one pass.  `forced_regs_avoid` lists tile-local positions a
+// stage should not use as register bits when it has the choice.
+void plan_stages(HostPass& pass, int r);
+
+// Full streaming plan: sequence, passes, period search, stages.
+StreamPlan plan_stream(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
+                       int observed, bool merge, const PassParams& pp);
+
+// Plan for a state that fits one workgroup: stages over all M sites for the
+// prologue (observable of step 0) and for one periodic step (factors, then
+// the observable).  No merging across step boundaries, so every step is
+// identical.
+struct ResidentPlan {
+    HostPass prologue;
+    HostPass step;
+};
+ResidentPlan plan_resident(int M, const std::vector<Coupling>& J, double dt, int observed,
+                           bool merge, int r);
+
+// Encoded device tables.
+template <typename T>
+struct DevTables {
+    std::vector<DevPass> passes;
+    std::vector<DevStage> stages;
+    std::vector<DevOp<T>> ops;
+};
+
+template <typename T>
+void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, int vec,
+                 DevTables<T>& out);
+
+std::string describe_plan(const StreamPlan& plan);
+
+}  // namespace spinqp

@@ -1,0 +1,232 @@
+"""Parity of the HIP path with the CPU oracle, element by element.
+
+Small and mid sizes (several tiles, every kernel path, edge cases).  FP64
+states must match the oracle's Trotter loop within 1e-10 on every P[k]
+and every amplitude; FP32 states within 1e-4 on P[k] (amplitudes within
+1e-4 of the largest).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import cref
+import paper_0710_3747_amd as spq
+from gpu_helpers import TOL_P, assert_state_close, gpu_evolve, gpu_state, note
+
+pytestmark = pytest.mark.gpu
+C64, C128 = spq.SPIN_C64, spq.SPIN_C128
+PRECS = [C128, C64]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    spq.load_library()
+    cref.build(force=False)
+    yield
+    torch.cuda.synchronize()
+
+
+def oracle_run(M, J, dt, steps, obs, pol=0, seed=1, psi0=None):
+    psi = oracle.random_phase_state(M, pol, seed) if psi0 is None else psi0.astype(np.complex128).copy()
+    psi = np.ascontiguousarray(psi)
+    P, N = cref.trotter_run(psi, M, J, dt, steps, obs)
+    return P, N, psi
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,n,seed", [(1, 0, 3), (2, 1, 0), (7, 3, 2 ** 64 - 1), (14, 13, 5), (21, 0, 99)])
+def test_init_matches_oracle(prec, M, n, seed):
+    note("init", prec, M, n, seed)
+    import torch
+    psi = gpu_state(prec, M, n, seed)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().astype(np.complex128)
+    want = oracle.random_phase_state(M, n, seed)
+    tol = 1e-15 if prec == C128 else 1e-7
+    assert np.abs(got - want).max() <= tol * np.abs(want).max() * 4
+
+
+def test_init_phase_golden_vectors():
+    """Phases of the GPU state reproduce stored generator outputs."""
+    import os
+    import torch
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden", "phase_vectors.txt"))
+            if not l.startswith("#")]
+    M = 13
+    for seed in sorted({int(r[0]) for r in rows})[:4]:
+        psi = gpu_state(C128, M, 0, seed)
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy()
+        for s, r, _, u in rows:
+            if int(s) != seed or int(r) >= 2 ** (M - 1):
+                continue
+            x = int(r) << 1          # polarised site 0: x = r with a 0 inserted at bit 0
+            phi = 2 * np.pi * float(u)
+            assert abs(got[x] * np.sqrt(2.0 ** (M - 1)) - np.exp(1j * phi)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_local_polarization(prec):
+    import torch
+    M = 17
+    psi0 = oracle.random_phase_state(M, 4, 8)
+    psi0 = psi0 * np.exp(0.3j * (np.arange(2 ** M) % 7))  # any state
+    rng = np.random.default_rng(0)
+    psi0 = psi0 + 1e-3 * (rng.standard_normal(2 ** M) + 1j * rng.standard_normal(2 ** M))
+    psi = gpu_state(prec, M, psi0=psi0)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for site in (0, 4, 16):
+        note("observe", prec, site)
+        spq.spin_local_polarization(psi, M, site, out)
+        torch.cuda.synchronize()
+        ref_state = psi.cpu().numpy().astype(np.complex128)
+        P, N = out.cpu().numpy()
+        assert abs(P - oracle.local_polarization(ref_state, M, site)) < 1e-12
+        assert abs(N - oracle.norm2(ref_state)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config_ladder_2x5_full(prec):
+    """Ladder 2x5, J = 1, dt = 0.05, 400 steps, site 0 polarised (whole
+    state in one workgroup)."""
+    M, (L, dt, steps, seed) = 10, workloads.LADDER_CONFIGS["ladder_2x5"]
+    J = workloads.ladder(L)
+    note("ladder 2x5", prec)
+    P, N, psi, _ = gpu_evolve(prec, M, J, dt, steps, 0, seed=seed)
+    Pw, Nw, psiw = oracle_run(M, J, dt, steps, 0, seed=seed)
+    assert np.abs(P - Pw).max() < TOL_P[prec]
+    assert np.abs(N - Nw).max() < TOL_P[prec]
+    assert_state_close(psi, psiw, prec)
+
+
+TILED = [
+    # name, M, couplings, dt, steps, observed, polarized, options
+    ("ladder16", 16, workloads.ladder(8), 0.05, 25, 0, 0, {}),
+    ("ladder16-k12", 16, workloads.ladder(8), 0.05, 25, 0, 0, {"tile_bits": 12}),
+    ("ladder18-periodic", 18, workloads.ladder(9), 0.05, 110, 0, 0, {}),
+    ("star16-k13", 16, workloads.star(16, 4), 0.02, 8, 0, 0, {"tile_bits": 13}),
+    ("star15-zz-obs3", 15, workloads.star(15, 5, a_over_b=-2.0), 0.03, 6, 3, 1, {}),
+    ("mixed17-r4", 17, workloads.ladder(8, a_over_b=0.7) + [(2, 16, 0.3, -1.1), (0, 16, 0.0, 0.4)],
+     0.05, 10, 16, 16, {"reg_bits": 4, "tile_bits": 12}),
+    ("uncoupled-observed-periodic", 16, [(1, 2, 0.0, 1.0), (5, 15, 0.0, 1.0)], 0.1, 100, 0, 0, {}),
+    ("no-couplings", 15, [], 0.1, 5, 3, 0, {}),
+    ("large-angles", 15, [(0, 1, 3.0, 40.0), (1, 14, 0.0, -35.0), (3, 9, 0.0, 100.0)], 0.1, 6, 0, 0, {}),
+    ("duplicate-pairs", 15, workloads.chain(15) + [(0, 1, 0.0, 1.0), (1, 0, 0.0, 0.5)], 0.05, 12, 1, 0, {}),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", TILED, ids=[c[0] for c in TILED])
+def test_tiled_path_matches_oracle(prec, case):
+    name, M, J, dt, steps, obs, pol, opts = case
+    if prec == C128 and opts.get("tile_bits", 0) > 13:
+        pytest.skip("complex128 tiles hold at most 2^13 amplitudes")
+    if prec == C64 and opts.get("reg_bits") == 4 and opts.get("tile_bits") not in (None, 12):
+        pytest.skip("no such complex64 shape")
+    note("tiled", name, prec)
+    info = spq.spin_describe_plan(prec, M, J, dt, steps, obs, spq.Options(**opts))
+    assert info["path"] == 2
+    P, N, psi, _ = gpu_evolve(prec, M, J, dt, steps, obs, polarized=pol, seed=7, opts=opts)
+    Pw, Nw, psiw = oracle_run(M, J, dt, steps, obs, pol=pol, seed=7)
+    assert np.abs(P - Pw).max() < TOL_P[prec]
+    assert np.abs(N - Nw).max() < TOL_P[prec]
+    assert_state_close(psi, psiw, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M", [1, 2, 3, 6, 11, 13, 14])
+def test_small_states_one_workgroup(prec, M):
+    """Every size of the one-workgroup path, including M = 1 (no bonds)."""
+    if prec == C128 and M == 14:
+        M = 13
+    J = [(i, j, 0.0, 1.0) for i in range(M) for j in range(i + 1, M) if (i + j) % 3 != 1][: 3 * M]
+    note("small", prec, M, len(J))
+    P, N, psi, _ = gpu_evolve(prec, M, J, 0.07, 30, 0, seed=M)
+    Pw, Nw, psiw = oracle_run(M, J, 0.07, 30, 0, seed=M)
+    assert np.abs(P - Pw).max() < TOL_P[prec]
+    assert_state_close(psi, psiw, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,j", [(2, 1), (16, 15), (20, 19)])
+def test_single_bond_closed_form(prec, M, j):
+    """Only bond (0, j): P(t) = (1 + cos(b t))/2 exactly (any a, seed, dt)."""
+    b, dt, steps = 1.7, 0.05, 120
+    note("single bond", prec, M, j)
+    P, N, _, _ = gpu_evolve(prec, M, [(0, j, 0.4, b)], dt, steps, 0, seed=3, keep_state=False)
+    k = np.arange(steps + 1)
+    assert np.abs(P - 0.5 * (1 + np.cos(b * k * dt))).max() < TOL_P[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_unfused_schedule_matches_oracle_and_fused(prec):
+    M, J = 15, workloads.ladder(7) + [(0, 14, 0.5, 0.8)]
+    note("unfused", prec)
+    Pu, _, psiu, _ = gpu_evolve(prec, M, J, 0.05, 8, 0, opts={"schedule": 1})
+    Pf, _, psif, _ = gpu_evolve(prec, M, J, 0.05, 8, 0)
+    Pw, _, psiw = oracle_run(M, J, 0.05, 8, 0)
+    assert np.abs(Pu - Pw).max() < TOL_P[prec] and np.abs(Pf - Pw).max() < TOL_P[prec]
+    assert_state_close(psiu, psiw, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_zero_steps_and_time_reversal(prec):
+    M, J = 16, workloads.star(16, 9)
+    note("reversal", prec)
+    P0, _, psi_same, _ = gpu_evolve(prec, M, J, 0.05, 0, 0, seed=4)
+    psi0 = oracle.random_phase_state(M, 0, 4)
+    assert_state_close(psi_same, psi0, prec)
+    assert abs(P0[0] - 1) < TOL_P[prec]
+    _, _, _, t = gpu_evolve(prec, M, J, 0.05, 20, 0, seed=4, keep_state=False)
+    _, _, back, _ = gpu_evolve(prec, M, J, -0.05, 20, 0, psi=t)
+    assert np.abs(back - psi0).max() < (1e-12 if prec == C128 else 1e-5) * np.abs(psi0).max() * 100
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_determinism_bitwise(prec):
+    M, J = 17, workloads.ladder(8) + [(0, 16, 0.0, 1.0)]
+    note("determinism", prec)
+    P1, N1, s1, _ = gpu_evolve(prec, M, J, 0.05, 30, 0, seed=2)
+    P2, N2, s2, _ = gpu_evolve(prec, M, J, 0.05, 30, 0, seed=2)
+    assert np.array_equal(P1, P2) and np.array_equal(N1, N2) and np.array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_chunked_run_equals_single_run(prec):
+    """Resuming from the state buffer (two calls) gives the same dynamics."""
+    M, J = 16, workloads.ladder(8)
+    note("chunked", prec)
+    P, _, psi, _ = gpu_evolve(prec, M, J, 0.05, 60, 0, seed=6)
+    Pa, _, _, t = gpu_evolve(prec, M, J, 0.05, 25, 0, seed=6, keep_state=False)
+    Pb, _, psib, _ = gpu_evolve(prec, M, J, 0.05, 35, 0, psi=t)
+    assert np.abs(np.concatenate([Pa, Pb[1:]]) - P).max() < TOL_P[prec]
+    assert_state_close(psib, psi, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_matches_single_runs(prec):
+    import torch
+    probs_spec = workloads.star_batch(12, 5, 13 if prec == C128 else 14, 4, 500, 600)
+    steps, dt = 40, 0.02
+    probs = []
+    for r, p in enumerate(probs_spec):
+        M = p["M"]
+        probs.append(dict(psi=torch.empty(2 ** M, dtype=torch.complex64 if prec == C64 else torch.complex128,
+                                          device="cuda"),
+                          M=M, couplings=p["couplings"], observed_site=0, polarized_site=0, seed=p["seed"],
+                          P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"),
+                          N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
+    note("batch", prec, [p["M"] for p in probs])
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    torch.cuda.synchronize()
+    for p in probs:
+        P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+        assert np.array_equal(p["P"].cpu().numpy(), P)
+        assert np.array_equal(p["psi"].cpu().numpy().astype(np.complex128), psi)
+    # and one against the oracle
+    p = probs[0]
+    Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+    assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
