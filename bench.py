@@ -39,7 +39,7 @@ def ladder_workload():
                 observed=0, polarized=0)
 
 
-def run_path(spq, torch, w, prec, steps, warmup):
+def run_path(spq, torch, w, prec, steps, warmup, opts=None):
     """Returns dict with timing, P (host) and plan info for one precision."""
     M, J, dt = w["M"], w["J"], w["dt"]
     dtype = torch.complex64 if prec == spq.SPIN_C64 else torch.complex128
@@ -50,18 +50,18 @@ def run_path(spq, torch, w, prec, steps, warmup):
     stream = torch.cuda.current_stream()
     if warmup > 0:
         spq.spin_init_random_phase(psi, M, w["polarized"], w["seed"])
-        spq.spin_trotter_evolve(psi, M, J, dt, warmup, w["observed"], Pw)
+        spq.spin_trotter_evolve_ex(psi, M, J, dt, warmup, w["observed"], Pw, None, opts)
     spq.spin_init_random_phase(psi, M, w["polarized"], w["seed"])
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    spq.spin_trotter_evolve(psi, M, J, dt, steps, w["observed"], P, N)
+    spq.spin_trotter_evolve_ex(psi, M, J, dt, steps, w["observed"], P, N, opts)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    info = spq.spin_describe_plan(prec, M, J, dt, steps, w["observed"])
+    info = spq.spin_describe_plan(prec, M, J, dt, steps, w["observed"], opts)
     out = dict(ms_total=ms, wall_s=wall, P=P.cpu().numpy(), N=N.cpu().numpy(), info=info)
     del psi
     torch.cuda.empty_cache()
@@ -108,6 +108,26 @@ def cpu_baseline(w, n_couplings=4):
                 seconds=sec)
 
 
+def copy_probe(torch, gib=4, reps=5):
+    """Plain device-to-device copy of `gib` GiB (torch's copy kernel): the
+    reference for the HBM byte counters and the achievable copy bandwidth."""
+    n = gib * 2 ** 30 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 4 / (ms / 1e3) / 1e9
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": ms,
+                      "copy_GBs": gbs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +135,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="both", choices=["c64", "c128", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-bits", type=int, default=0)
+    ap.add_argument("--reg-bits", type=int, default=0)
+    ap.add_argument("--coalesce-bits", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -125,17 +150,24 @@ def main():
     import torch
     import paper_0710_3747_amd as spq
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     spq.load_library()
     w = ladder_workload()
     steps, warmup = args.steps, args.warmup
 
+    opts = None
+    if args.tile_bits or args.reg_bits or args.coalesce_bits:
+        opts = spq.Options(tile_bits=args.tile_bits, reg_bits=args.reg_bits,
+                           coalesce_bits=args.coalesce_bits)
     res32 = res64 = None
     if args.prec in ("c64", "both"):
         print(f"[bench] complex64 path, {steps} steps", file=sys.stderr, flush=True)
-        res32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup)
+        res32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup, opts)
     if args.prec in ("c128", "both"):
         print(f"[bench] complex128 path, {steps} steps", file=sys.stderr, flush=True)
-        res64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup)
+        res64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup, opts)
 
     head = res32 if res32 is not None else res64
     head_bytes = 8 if res32 is not None else 16

@@ -19,6 +19,7 @@ SOURCES = ["kernels.hip", "planner.cpp", "abi.cpp", "batch.cpp"]
 ARCH = os.environ.get("SPINQP_ARCH", "gfx950")
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-mllvm", "-structurizecfg-skip-uniform-regions=true",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function"]
 

@@ -213,10 +213,10 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             ResidentPlan rp = plan_resident(key.M, J, key.dt, key.observed, key.merge != 0, dp->res_r);
             const int nthreads = 1 << std::max(0, key.M - dp->res_r);
             dp->pro_stage0 = 0;
-            encode_pass<T>(rp.prologue, key.M, key.observed, dp->res_r, nthreads, 1, tb);
+            encode_pass<T>(rp.prologue, key.M, key.observed, dp->res_r, nthreads, 1, tb, true);
             dp->pro_nstage = int(tb.stages.size());
             dp->step_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.step, key.M, key.observed, dp->res_r, nthreads, 1, tb);
+            encode_pass<T>(rp.step, key.M, key.observed, dp->res_r, nthreads, 1, tb, true);
             dp->step_nstage = int(tb.stages.size()) - dp->step_stage0;
             dp->stages_total = tb.stages.size();
         } else {
@@ -367,7 +367,9 @@ static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double
     for (size_t l = 0; l < nl; ++l) {
         const int t = dp->sp.launch_tmpl[l];
         const int64_t off = dp->sp.launch_offset[l];
-        HIP_TRY((launch_pass<T>(dp->shape, psi, static_cast<const DevPass*>(dp->d_passes),
+        PassShape shp = dp->shape;
+        shp.writes = dp->sp.passes[t].writes;
+        HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp->d_passes),
                                 static_cast<const DevStage*>(dp->d_stages),
                                 static_cast<const DevOp<T>*>(dp->d_ops), t, dp->tiles_per_wg,
                                 dp->nwg, part, off, ch, st)));

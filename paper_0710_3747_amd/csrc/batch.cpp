@@ -52,10 +52,10 @@ static int batch_resident(const spin_problem* probs, int32_t n, const std::vecto
             j.init = init ? 1 : 0;
             const int nthreads = 1 << std::max(0, pr.M - g.first.first);
             j.pro_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, g.first.first, nthreads, 1, tb);
+            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, g.first.first, nthreads, 1, tb, true);
             j.pro_nstage = int(tb.stages.size()) - j.pro_stage0;
             j.step_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.step, pr.M, pr.observed_site, g.first.first, nthreads, 1, tb);
+            encode_pass<T>(rp.step, pr.M, pr.observed_site, g.first.first, nthreads, 1, tb, true);
             j.step_nstage = int(tb.stages.size()) - j.step_stage0;
             jobs.push_back(j);
         }

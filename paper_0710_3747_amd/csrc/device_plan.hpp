@@ -45,8 +45,8 @@ struct DevStage {
     int32_t obs_tq;           // thread bit holding the observed site, or -1
     int32_t obs_mask;         // register-index mask of the observed site (0 if none)
     int32_t pad_;
-    int8_t tpos[16];          // tile-local position of thread bit q
-    uint32_t soff[64];        // swizzled LDS offset of register j (bits rpos)
+    uint32_t tmask[16];       // swizzled LDS byte offset of thread bit q (zero past ntb)
+    uint32_t rbit[8];         // swizzled LDS byte offset of register bit q
 };
 
 // One tiled pass over the whole state.
@@ -59,13 +59,18 @@ struct DevPass {
     int32_t nmeas;            // measurements in this pass
     int32_t pad_;
     int64_t meas_step[kMaxMeas];   // step label of measurement slot m (plus launch offset)
-    int8_t tbit[16];          // global bit of tile-local position p
-    int8_t fbit[kMaxSites];   // global bits not in the tile, increasing
-    int64_t iter_goff[64];    // global element offset of load/store iteration it
-    uint32_t iter_soff[64];   // swizzled LDS offset of load/store iteration it
+    int32_t tbit[16];         // global bit of tile-local position p
+    int32_t fbit[kMaxSites];  // global bits not in the tile, increasing (zero-padded)
+    int64_t free_mask;        // mask of the global bits not in the tile
+    // load/store iterations: element e = it*NT*V + lane*V; iteration bit b
+    // of `it` sits at tile position log2(NT*V) + b
+    int64_t it_gbit[8];       // global element offset of iteration bit b
+    uint32_t it_lbit[8];      // LDS byte offset of iteration bit b
+    uint32_t ld_tmask[16];    // LDS byte offset of lane bit q in the load/store layout
 };
 
-// LDS swizzle: xor a band of higher local-index bits into the lowest bits
+// Fixed LDS swizzle of the one-workgroup kernel (tiled passes use a layout
+// searched per pass, see encode_pass): xor a band of higher local-index bits into the lowest bits
 // so that lanes striding by a power of two spread over the banks.  It is
 // linear over GF(2): swz(a ^ b) = swz(a) ^ swz(b).
 template <int ElemBytes>

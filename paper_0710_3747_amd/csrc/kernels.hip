@@ -178,46 +178,47 @@ __global__ __launch_bounds__(256) void k_factor(typename CT<T>::c* __restrict__ 
 // ------------------------------------------------------- register ops
 // Rotation of the anti-aligned pairs (bit A, bit B) = (0, 1) <-> (1, 0) of
 // the register index: psi_x <- c psi_x - i s psi_y, psi_y <- -i s psi_x + c psi_y,
-// done as two real three-shear rotations (exactly area preserving).
-template <int R, int A, int B, typename T>
-__device__ __forceinline__ void reg_xy(T (&re)[1 << R], T (&im)[1 << R], T t, T s) {
+// done as two real three-shear rotations (exactly area preserving):
+// (Re x, Im y) by [[c, s], [-s, c]] and (Im x, Re y) by [[c, -s], [s, c]],
+// each as u += t v; v -= s u; u += t v with t = tan(theta/2).
+template <int R, int A, int B, typename C, typename T>
+__device__ __forceinline__ void reg_xy(C (&v)[1 << R], T t, T s) {
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
         if (((j >> A) & 1) == 0 && ((j >> B) & 1) == 1) {
             const int k = j ^ (1 << A) ^ (1 << B);
-            T u = re[j], v = im[k];
-            u = fma(t, v, u); v = fma(-s, u, v); u = fma(t, v, u);
-            re[j] = u; im[k] = v;
-            u = im[j]; v = re[k];
-            u = fma(-t, v, u); v = fma(s, u, v); u = fma(-t, v, u);
-            im[j] = u; re[k] = v;
+            T u = v[j].x, w = v[k].y;
+            u = fma(t, w, u); w = fma(-s, u, w); u = fma(t, w, u);
+            v[j].x = u; v[k].y = w;
+            u = v[j].y; w = v[k].x;
+            u = fma(-t, w, u); w = fma(s, u, w); u = fma(-t, w, u);
+            v[j].y = u; v[k].x = w;
         }
     }
 }
 
 // I^z I^z phase: anti-aligned amplitudes times (pr + i pi), aligned times
 // its conjugate.
-template <int R, int A, int B, typename T>
-__device__ __forceinline__ void reg_zz(T (&re)[1 << R], T (&im)[1 << R], T pr, T pim) {
+template <int R, int A, int B, typename C, typename T>
+__device__ __forceinline__ void reg_zz(C (&v)[1 << R], T pr, T pim) {
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
         const bool anti = ((j >> A) & 1) != ((j >> B) & 1);
         const T q = anti ? pim : -pim;
-        const T x = re[j], y = im[j];
-        re[j] = fma(pr, x, -q * y);
-        im[j] = fma(pr, y, q * x);
+        const T x = v[j].x, y = v[j].y;
+        v[j].x = fma(pr, x, -q * y);
+        v[j].y = fma(pr, y, q * x);
     }
 }
 
-template <int R, typename T>
-__device__ __forceinline__ void reg_op(T (&re)[1 << R], T (&im)[1 << R], int code, T t, T s,
-                                       T pr, T pim) {
-#define SPIN_CASE(A, B)                                   \
-    case A * 8 + B:                                       \
-        if constexpr (B < R) {                            \
-            reg_xy<R, A, B>(re, im, t, s);                \
-            if (code & kOpZZ) reg_zz<R, A, B>(re, im, pr, pim); \
-        }                                                 \
+template <int R, typename C, typename T>
+__device__ __forceinline__ void reg_op(C (&v)[1 << R], int code, T t, T s, T pr, T pim) {
+#define SPIN_CASE(A, B)                                        \
+    case A * 8 + B:                                            \
+        if constexpr (B < R) {                                 \
+            reg_xy<R, A, B>(v, t, s);                          \
+            if (code & kOpZZ) reg_zz<R, A, B>(v, pr, pim);     \
+        }                                                      \
         break;
     switch (code & 63) {
         SPIN_CASE(0, 1) SPIN_CASE(0, 2) SPIN_CASE(1, 2) SPIN_CASE(0, 3) SPIN_CASE(1, 3)
@@ -229,20 +230,105 @@ __device__ __forceinline__ void reg_op(T (&re)[1 << R], T (&im)[1 << R], int cod
 }
 
 // sum of (sign * |psi|^2, |psi|^2) over the lane's registers, FP64
-template <int R, typename T>
-__device__ __forceinline__ void reg_observe(const T (&re)[1 << R], const T (&im)[1 << R], int sign,
-                                            int mask, double& p, double& n) {
+template <int R, typename C>
+__device__ __forceinline__ void reg_observe(const C (&v)[1 << R], int sign, int mask, double& p,
+                                            double& n) {
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
-        const double w = double(re[j]) * double(re[j]) + double(im[j]) * double(im[j]);
+        const double w = double(v[j].x) * double(v[j].x) + double(v[j].y) * double(v[j].y);
         n += w;
         const int neg = sign ^ ((j & mask) ? 1 : 0);
         p += neg ? -w : w;
     }
 }
 
+// LDS byte address of the lane's register 0 in stage S (thread bits only;
+// entries past the stage's thread bits are zero).
+__device__ __forceinline__ uint32_t stage_base(const DevStage& S, int tid) {
+    uint32_t b = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) b ^= S.tmask[q] & (0u - ((uint32_t(tid) >> q) & 1u));
+    return b;
+}
+
+// Barrier for LDS traffic only: global loads in flight (the next tile's
+// prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Deposit of the bits of `x` into the set bits of `mask`, lowest first.
+__device__ __forceinline__ int64_t deposit(int64_t x, int64_t mask) {
+    int64_t out = 0;
+    while (x && mask) {
+        const int64_t low = mask & -mask;
+        if (x & 1) out |= low;
+        mask ^= low;
+        x >>= 1;
+    }
+    return out;
+}
+
+// Next value, in increasing order, among the submasks of `mask`.
+__device__ __forceinline__ int64_t next_submask(int64_t cur, int64_t mask) {
+    return ((cur | ~mask) + 1) & mask;
+}
+
+// Gather / scatter of a lane's 2^R registers in Gray-code order: register
+// j = i ^ (i >> 1) sits at pb ^ (xor of rbit[q] over the set bits q of j),
+// and consecutive Gray codes differ in bit ctz(i).
+template <int R, typename C>
+__device__ __forceinline__ void gather(C (&v)[1 << R], const char* lds, uint32_t pb,
+                                       const DevStage& S) {
+    uint32_t a = pb;
+    v[0] = *reinterpret_cast<const C*>(lds + a);
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) {
+        a ^= S.rbit[__builtin_ctz(i)];
+        v[i ^ (i >> 1)] = *reinterpret_cast<const C*>(lds + a);
+    }
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void scatter(const C (&v)[1 << R], char* lds, uint32_t pb,
+                                        const DevStage& S) {
+    uint32_t a = pb;
+    *reinterpret_cast<C*>(lds + a) = v[0];
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) {
+        a ^= S.rbit[__builtin_ctz(i)];
+        *reinterpret_cast<C*>(lds + a) = v[i ^ (i >> 1)];
+    }
+}
+
+// Runs ops from index o up to the stage end o1 or the next observable op
+// (whichever comes first) on the lane's registers; returns the index of
+// the first op not run.  Each op's record is loaded one op ahead.
+template <int R, typename C, typename T>
+__device__ __forceinline__ int run_factors(C (&v)[1 << R], const DevOp<T>* __restrict__ ops, int o,
+                                           int o1) {
+    if (o >= o1) return o;
+    DevOp<T> cur = ops[o];
+    while (cur.code != kOpMeas) {
+        const int on = o + 1;
+        const DevOp<T> nxt = ops[on < o1 ? on : o];
+        reg_op<R>(v, cur.code, cur.t, cur.s, cur.pr, cur.pi);
+        o = on;
+        if (o >= o1) break;
+        cur = nxt;
+    }
+    return o;
+}
+
+template <typename C>
+__device__ __forceinline__ C& lds_at(char* lds, uint32_t byte) {
+    return *reinterpret_cast<C*>(lds + byte);
+}
+
 // --------------------------------------------------------------- k_pass
-template <typename T, int R, int NT>
+template <typename T, int R, int NT, bool WRITES>
 __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi,
                                              const DevPass* __restrict__ passes,
                                              const DevStage* __restrict__ stages,
@@ -260,8 +346,10 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
 
     const DevPass& P = passes[pass_index];
     const int tid = threadIdx.x;
+    char* ldsb = reinterpret_cast<char*>(lds);
 
-    // per-lane load/store offsets: element e = it*NT*V + tid*V (+ v)
+    // per-lane load/store offsets: element e = it*NT*V + tid*V (+ v); the
+    // iterations walk `it` in Gray-code order
     int64_t goff_t = 0;
     {
         const uint32_t e = uint32_t(tid) * V;
@@ -269,99 +357,128 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
         for (int p = 0; p < K; ++p)
             if (e & (1u << p)) goff_t |= int64_t(1) << P.tbit[p];
     }
-    const uint32_t soff_t = lds_swizzle<EB>(uint32_t(tid) * V);
+    uint32_t soff_t = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) soff_t ^= P.ld_tmask[q] & (0u - ((uint32_t(tid) >> q) & 1u));
 
     double accP[kMaxMeas], accN[kMaxMeas];
 #pragma unroll
     for (int m = 0; m < kMaxMeas; ++m) accP[m] = accN[m] = 0.0;
 
-    for (int64_t it_tile = 0; it_tile < tiles_per_wg; ++it_tile) {
-        const int64_t tile = int64_t(blockIdx.x) + it_tile * int64_t(gridDim.x);
-        int64_t base = 0;
-        for (int f = 0; f < P.nfree; ++f)
-            if ((tile >> f) & 1) base |= int64_t(1) << P.fbit[f];
+    // Tile bases: tile = blockIdx.x + i * gridDim.x with gridDim.x a power
+    // of two, so base = deposit(blockIdx.x) | (i-th submask of the free
+    // bits above the lowest log2(gridDim.x) ones).
+    // XCD-aware order: workgroups are dispatched round-robin over the 8
+    // XCDs, so w and w + 8 share an L2.  They take adjacent tile indices,
+    // i.e. tiles that differ only in the lowest non-tile address bit and so
+    // share cache lines when the tile's contiguous runs are shorter than a
+    // line.
+    const unsigned G = gridDim.x, w = blockIdx.x;
+    const unsigned wperm = (G >= 8) ? (w % 8u) * (G / 8u) + w / 8u : w;
+    const int64_t base_wg = deposit(wperm, P.free_mask);
+    int64_t m_hi = P.free_mask;
+    for (unsigned g = gridDim.x; g > 1; g >>= 1) m_hi &= m_hi - 1;
+
+    // The next tile is loaded into `pre` while the current one is worked on
+    // in LDS; barriers below only wait for LDS traffic.
+    VEC pre[NIT];
+    auto prefetch = [&](int64_t base) {
+        int64_t g = base + goff_t;
+        pre[0] = *reinterpret_cast<const VEC*>(psi + g);
+#pragma unroll
+        for (int i = 1; i < NIT; ++i) {
+            g ^= P.it_gbit[__builtin_ctz(i)];
+            pre[i ^ (i >> 1)] = *reinterpret_cast<const VEC*>(psi + g);
+        }
+    };
+    int64_t hi = 0;
+    prefetch(base_wg);
+
+    // One tile: prefetched registers -> LDS, stages, LDS -> global.  The
+    // next tile's loads are issued right after the LDS fill and are always
+    // issued (the last tile re-reads itself) so that every iteration ends
+    // with the same memory ops outstanding -- prefetch loads, then stores --
+    // and the fill only waits for the loads.
+    auto tile_body = [&](int64_t it_tile) {
+        const int64_t base = base_wg | hi;
         const int tile_sign = P.obs_free_bit >= 0 ? int((base >> P.obs_free_bit) & 1) : 0;
 
-        // global -> LDS
+        // prefetched registers -> LDS
         {
-            VEC buf[NIT];
+            uint32_t a = soff_t;
 #pragma unroll
-            for (int it = 0; it < NIT; ++it)
-                buf[it] = *reinterpret_cast<const VEC*>(psi + base + goff_t + P.iter_goff[it]);
-#pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const uint32_t a = soff_t ^ P.iter_soff[it];
+            for (int i = 0; i < NIT; ++i) {
+                if (i) a ^= P.it_lbit[__builtin_ctz(i)];
+                const VEC& w = pre[i ^ (i >> 1)];
                 if constexpr (V == 2) {
-                    C lo, hi;
-                    lo.x = buf[it].x; lo.y = buf[it].y;
-                    hi.x = buf[it].z; hi.y = buf[it].w;
-                    lds[a] = lo;
-                    lds[a ^ 1] = hi;
+                    C lo, hi2;
+                    lo.x = w.x; lo.y = w.y;
+                    hi2.x = w.z; hi2.y = w.w;
+                    lds_at<C>(ldsb, a) = lo;
+                    lds_at<C>(ldsb, a ^ EB) = hi2;
                 } else {
                     C c;
-                    c.x = buf[it].x; c.y = buf[it].y;
-                    lds[a] = c;
+                    c.x = w.x; c.y = w.y;
+                    lds_at<C>(ldsb, a) = c;
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
+        if (it_tile + 1 < tiles_per_wg) hi = next_submask(hi, m_hi);
+        prefetch(base_wg | hi);
 
         for (int si = 0; si < P.nstage; ++si) {
             const DevStage& S = stages[P.stage0 + si];
-            uint32_t lb = 0;
-            for (int q = 0; q < S.ntb; ++q)
-                if ((tid >> q) & 1) lb |= 1u << S.tpos[q];
-            const uint32_t pb = lds_swizzle<EB>(lb);
-            T re[1 << R], im[1 << R];
-#pragma unroll
-            for (int j = 0; j < (1 << R); ++j) {
-                const C c = lds[pb ^ S.soff[j]];
-                re[j] = c.x;
-                im[j] = c.y;
-            }
+            const uint32_t pb = stage_base(S, tid);
+            C v[1 << R];
+            gather<R>(v, ldsb, pb, S);
             const int sign = tile_sign ^ (S.obs_tq >= 0 ? ((tid >> S.obs_tq) & 1) : 0);
-            for (int o = S.op0; o < S.op0 + S.nop; ++o) {
-                const DevOp<T> op = ops[o];
-                if (op.code == kOpMeas) {
+            const int o1 = S.op0 + S.nop;
+            int o = S.op0;
+            while (o < o1) {
+                o = run_factors<R>(v, ops, o, o1);
+                if (o < o1) {    // observable of the state at this point
+                    const int slot = ops[o].aux;
                     double p = 0.0, n = 0.0;
-                    reg_observe<R, T>(re, im, sign, S.obs_mask, p, n);
+                    reg_observe<R>(v, sign, S.obs_mask, p, n);
 #pragma unroll
                     for (int m = 0; m < kMaxMeas; ++m)
-                        if (m == op.aux) { accP[m] += p; accN[m] += n; }
-                } else {
-                    reg_op<R, T>(re, im, op.code, op.t, op.s, op.pr, op.pi);
+                        if (m == slot) { accP[m] += p; accN[m] += n; }
+                    ++o;
                 }
             }
             // A lane scatters to exactly the LDS slots it gathered, so the
             // only hazard is with the next stage's gathers (barrier below).
-#pragma unroll
-            for (int j = 0; j < (1 << R); ++j) {
-                C c;
-                c.x = re[j];
-                c.y = im[j];
-                lds[pb ^ S.soff[j]] = c;
-            }
-            __syncthreads();
+            scatter<R>(v, ldsb, pb, S);
+            lds_barrier();
         }
 
-        // LDS -> global
-        if (P.writes) {
+        // LDS -> global (a template switch, not a branch, so the number of
+        // memory ops in flight is the same on every path)
+        if constexpr (WRITES) {
+            uint32_t a = soff_t;
+            int64_t g = base + goff_t;
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const uint32_t a = soff_t ^ P.iter_soff[it];
-                VEC v;
-                if constexpr (V == 2) {
-                    const C lo = lds[a], hi = lds[a ^ 1];
-                    v.x = lo.x; v.y = lo.y; v.z = hi.x; v.w = hi.y;
-                } else {
-                    const C c = lds[a];
-                    v.x = c.x; v.y = c.y;
+            for (int i = 0; i < NIT; ++i) {
+                if (i) {
+                    a ^= P.it_lbit[__builtin_ctz(i)];
+                    g ^= P.it_gbit[__builtin_ctz(i)];
                 }
-                *reinterpret_cast<VEC*>(psi + base + goff_t + P.iter_goff[it]) = v;
+                VEC w;
+                if constexpr (V == 2) {
+                    const C lo = lds_at<C>(ldsb, a), hi2 = lds_at<C>(ldsb, a ^ EB);
+                    w.x = lo.x; w.y = lo.y; w.z = hi2.x; w.w = hi2.y;
+                } else {
+                    const C c = lds_at<C>(ldsb, a);
+                    w.x = c.x; w.y = c.y;
+                }
+                *reinterpret_cast<VEC*>(psi + g) = w;
             }
         }
-        __syncthreads();
-    }
+        lds_barrier();
+    };
+    tile_body(0);
+    for (int64_t it_tile = 1; it_tile < tiles_per_wg; ++it_tile) tile_body(it_tile);
 
     for (int m = 0; m < P.nmeas; ++m) {
         double p = accP[0], n = accN[0];
@@ -399,6 +516,7 @@ __global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
     const int nact = (M >= R) ? (1 << (M - R)) : 1;
     C* psi = reinterpret_cast<C*>(J.psi);
 
+    char* ldsb = reinterpret_cast<char*>(lds);
     if (J.init) {
         const double scale = 1.0 / sqrt(ldexp(1.0, M - 1));
         for (uint32_t x = tid; x < dim; x += NT) {
@@ -417,47 +535,33 @@ __global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
     auto run = [&](int st0, int nst, int64_t step) {
         for (int si = st0; si < st0 + nst; ++si) {
             const DevStage& S = stages[si];
-            uint32_t lb = 0;
-            for (int q = 0; q < S.ntb; ++q)
-                if ((tid >> q) & 1) lb |= 1u << S.tpos[q];
-            const uint32_t pb = lds_swizzle<EB>(lb);
+            // Lanes past the state's size shadow an active lane (same LDS
+            // slots) so that the op loop below stays free of divergence;
+            // they never scatter and contribute nothing to observables.
             const bool act = tid < nact;
-            T re[1 << R], im[1 << R];
-            if (act) {
-#pragma unroll
-                for (int j = 0; j < (1 << R); ++j) {
-                    const C c = lds[pb ^ S.soff[j]];
-                    re[j] = c.x;
-                    im[j] = c.y;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < (1 << R); ++j) re[j] = im[j] = T(0);
-            }
+            const uint32_t pb = stage_base(S, tid & (nact - 1));
+            C v[1 << R];
+            gather<R>(v, ldsb, pb, S);
             const int sign = S.obs_tq >= 0 ? ((tid >> S.obs_tq) & 1) : 0;
-            for (int o = S.op0; o < S.op0 + S.nop; ++o) {
-                const DevOp<T> op = ops[o];
-                if (op.code == kOpMeas) {
+            const int o1 = S.op0 + S.nop;
+            int o = S.op0;
+            while (o < o1) {
+                o = run_factors<R>(v, ops, o, o1);
+                if (o < o1) {    // observable: reduce over the workgroup now
                     double p = 0.0, n = 0.0;
-                    reg_observe<R, T>(re, im, sign, S.obs_mask, p, n);
+                    reg_observe<R>(v, sign, S.obs_mask, p, n);
+                    p = act ? p : 0.0;
+                    n = act ? n : 0.0;
                     block_sum2<NT>(p, n, red);
                     if (tid == 0) {
                         J.P[step] = p;
                         if (J.N) J.N[step] = n;
                     }
-                } else {
-                    reg_op<R, T>(re, im, op.code, op.t, op.s, op.pr, op.pi);
+                    ++o;
                 }
             }
-            if (act) {
-#pragma unroll
-                for (int j = 0; j < (1 << R); ++j) {
-                    C c;
-                    c.x = re[j];
-                    c.y = im[j];
-                    lds[pb ^ S.soff[j]] = c;
-                }
-            }
+            __syncthreads();    // every shadow lane has gathered
+            if (act) scatter<R>(v, ldsb, pb, S);
             __syncthreads();
         }
     };
@@ -511,12 +615,17 @@ hipError_t launch_factor(void* psi, int M, int lo, int hi, double t, double s, d
 }
 
 template <typename T, int R, int NT>
-static hipError_t pass_one(void* psi, const DevPass* passes, const DevStage* stages,
+static hipError_t pass_one(bool writes, void* psi, const DevPass* passes, const DevStage* stages,
                            const DevOp<T>* ops, int pass_index, int64_t tiles_per_wg, int nwg,
                            double* partials, int64_t step_offset, int ch, hipStream_t st) {
-    hipLaunchKernelGGL((k_pass<T, R, NT>), dim3(nwg), dim3(NT), 0, st,
-                       reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops, pass_index,
-                       tiles_per_wg, partials, step_offset, ch, nwg);
+    if (writes)
+        hipLaunchKernelGGL((k_pass<T, R, NT, true>), dim3(nwg), dim3(NT), 0, st,
+                           reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
+                           pass_index, tiles_per_wg, partials, step_offset, ch, nwg);
+    else
+        hipLaunchKernelGGL((k_pass<T, R, NT, false>), dim3(nwg), dim3(NT), 0, st,
+                           reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
+                           pass_index, tiles_per_wg, partials, step_offset, ch, nwg);
     return hipGetLastError();
 }
 
@@ -527,7 +636,7 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
                        int ch, hipStream_t st) {
 #define SPIN_PASS(RR, NTT)                                                                   \
     if (sh.r == RR && sh.nt == NTT)                                                          \
-        return pass_one<T, RR, NTT>(psi, passes, stages, ops, pass_index, tiles_per_wg, nwg, \
+        return pass_one<T, RR, NTT>(sh.writes, psi, passes, stages, ops, pass_index, tiles_per_wg, nwg, \
                                     partials, step_offset, ch, st);
     if constexpr (sizeof(T) == 4) {
         SPIN_PASS(5, 256) SPIN_PASS(5, 512) SPIN_PASS(4, 256) SPIN_PASS(6, 256)

@@ -22,6 +22,7 @@ struct ResidentJob {
 struct PassShape {
     int r;    // register bits (amplitudes per lane = 2^r)
     int nt;   // lanes per workgroup; tile bits k = r + log2(nt)
+    bool writes = true;   // false: read-only pass (observables only)
 };
 
 template <typename T>

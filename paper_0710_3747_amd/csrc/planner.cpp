@@ -528,9 +528,71 @@ ResidentPlan plan_resident(int M, const std::vector<Coupling>& J, double dt, int
 }
 
 // ----------------------------------------------------------------- encode
+namespace {
+
+// Rank over GF(2) of a small set of bit vectors.
+int gf2_rank(std::vector<uint32_t> v) {
+    int rank = 0;
+    for (int bitp = 31; bitp >= 0; --bitp) {
+        int piv = -1;
+        for (size_t i = rank; i < v.size(); ++i)
+            if (v[i] >> bitp & 1u) { piv = int(i); break; }
+        if (piv < 0) continue;
+        std::swap(v[rank], v[piv]);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (int(i) != rank && (v[i] >> bitp & 1u)) v[i] ^= v[rank];
+        ++rank;
+    }
+    return rank;
+}
+
+// LDS layout of one tiled pass: element index image of each tile-local
+// position p (phys(l) = xor of img[p] over the set bits of l).  Positions
+// below `nb` (the bank-slot bits: 32 slots of 8 bytes or 16 of 16 bytes in a
+// 256-byte bank row) map to themselves; higher positions also flip a
+// searched set of slot bits.  The search makes every access pattern of the
+// pass -- the load/store layout and each stage's gather -- map the lanes of
+// a 2^nb-lane group onto distinct slots (no bank conflicts).
+std::vector<uint32_t> search_layout(int k, int nb, const std::vector<std::vector<int>>& patterns,
+                                    uint64_t seed) {
+    std::vector<uint32_t> img(k), best;
+    int best_def = 1 << 30;
+    uint64_t st = seed * 0x9E3779B97F4A7C15ull + 1;
+    auto rnd = [&]() {
+        st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+        return st;
+    };
+    const uint32_t slot_mask = (1u << nb) - 1;
+    for (int attempt = 0; attempt < 4000; ++attempt) {
+        for (int p = 0; p < k; ++p)
+            img[p] = (1u << p) | (p >= nb && attempt > 0 ? uint32_t(rnd()) & slot_mask : 0u);
+        int def = 0;
+        for (const auto& pat : patterns) {
+            std::vector<uint32_t> v;
+            for (size_t q = 0; q < pat.size() && int(q) < nb; ++q) v.push_back(img[pat[q]] & slot_mask);
+            def += int(v.size()) - gf2_rank(v);
+        }
+        if (def < best_def) {
+            best_def = def;
+            best = img;
+            if (def == 0) break;
+        }
+    }
+    return best;
+}
+
+uint32_t apply_layout(const std::vector<uint32_t>& img, uint32_t l) {
+    uint32_t o = 0;
+    for (size_t p = 0; p < img.size(); ++p)
+        if (l >> p & 1u) o ^= img[p];
+    return o;
+}
+
+}  // namespace
+
 template <typename T>
 void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, int vec,
-                 DevTables<T>& out) {
+                 DevTables<T>& out, bool fixed_swizzle) {
     const int k = int(hp.sites.size());
     constexpr int eb = sizeof(T) * 2;
     DevPass dp{};
@@ -541,42 +603,60 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
     int nf = 0;
     std::vector<int> local(kMaxSites, -1);
     for (int p = 0; p < k; ++p) {
-        dp.tbit[p] = int8_t(hp.sites[p]);
+        dp.tbit[p] = hp.sites[p];
         local[hp.sites[p]] = p;
     }
     for (int s = 0; s < M; ++s)
-        if (local[s] < 0) dp.fbit[nf++] = int8_t(s);
+        if (local[s] < 0) {
+            dp.fbit[nf++] = s;
+            dp.free_mask |= int64_t(1) << s;
+        }
     dp.nfree = nf;
     dp.obs_free_bit = local[observed] < 0 ? observed : -1;
     // load/store iterations: element e = it*nthreads*vec + t*vec + v
     const int per_thread = (1 << k) / nthreads;     // amplitudes per lane
     const int nit = per_thread / vec;
-    if (nit > 64 || nit < 1) throw std::runtime_error("encode: bad iteration count");
-    for (int it = 0; it < nit; ++it) {
-        uint32_t e = uint32_t(it) * uint32_t(nthreads) * uint32_t(vec);
-        int64_t g = 0;
-        for (int p = 0; p < k; ++p)
-            if (e & (1u << p)) g |= int64_t(1) << hp.sites[p];
-        dp.iter_goff[it] = g;
-        dp.iter_soff[it] = lds_swizzle<eb>(e);
-    }
-    int nmeas = 0;
+    if (nit > 64 || nit < 1 || (nit & (nit - 1))) throw std::runtime_error("encode: bad iteration count");
+    const int lo = __builtin_ctz(unsigned(nthreads * vec));
+    const int vb = __builtin_ctz(unsigned(vec));
+
+    // thread positions of every stage, and the LDS layout
+    std::vector<std::vector<int>> tpos_all;
     for (const HostStage& hs : hp.stages) {
+        uint32_t rmask = 0;
+        for (int p : hs.regs) rmask |= 1u << p;
+        std::vector<int> tp;
+        for (int p = 0; p < k; ++p)
+            if (!(rmask & (1u << p))) tp.push_back(p);
+        tpos_all.push_back(tp);
+    }
+    std::vector<uint32_t> img(k);
+    if (fixed_swizzle) {
+        for (int p = 0; p < k; ++p) img[p] = lds_swizzle<eb>(1u << p);
+    } else {
+        std::vector<std::vector<int>> patterns = tpos_all;
+        std::vector<int> ld;
+        for (int q = 0; vb + q < lo; ++q) ld.push_back(vb + q);
+        patterns.push_back(ld);
+        img = search_layout(k, eb == 8 ? 5 : 4, patterns, uint64_t(k) * 131 + hp.ops.size());
+    }
+    auto byte_off = [&](uint32_t l) { return apply_layout(img, l) * uint32_t(eb); };
+    for (int b = 0; (1 << b) < nit; ++b) {
+        dp.it_gbit[b] = int64_t(1) << hp.sites[lo + b];
+        dp.it_lbit[b] = byte_off(1u << (lo + b));
+    }
+    for (int q = 0; vb + q < lo && q < 16; ++q) dp.ld_tmask[q] = byte_off(1u << (vb + q));
+
+    int nmeas = 0;
+    for (size_t si = 0; si < hp.stages.size(); ++si) {
+        const HostStage& hs = hp.stages[si];
         DevStage ds{};
         ds.op0 = int(out.ops.size());
         const int rr = int(hs.regs.size());
         ds.ntb = k - rr;
-        int q = 0;
-        uint32_t rmask = 0;
-        for (int p : hs.regs) rmask |= 1u << p;
-        for (int p = 0; p < k; ++p)
-            if (!(rmask & (1u << p))) ds.tpos[q++] = int8_t(p);
-        for (int j = 0; j < (1 << rr); ++j) {
-            uint32_t l = 0;
-            for (int b = 0; b < rr; ++b)
-                if (j & (1 << b)) l |= 1u << hs.regs[b];
-            ds.soff[j] = lds_swizzle<eb>(l);
-        }
+        const std::vector<int>& tq = tpos_all[si];
+        for (int q = 0; q < ds.ntb; ++q) ds.tmask[q] = byte_off(1u << tq[q]);
+        for (int b = 0; b < rr; ++b) ds.rbit[b] = byte_off(1u << hs.regs[b]);
         ds.obs_tq = -1;
         ds.obs_mask = 0;
         const int pobs = local[observed];
@@ -586,7 +666,7 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
                 if (hs.regs[b] == pobs) { ds.obs_mask = 1 << b; in_reg = true; }
             if (!in_reg)
                 for (int t = 0; t < ds.ntb; ++t)
-                    if (ds.tpos[t] == pobs) ds.obs_tq = t;
+                    if (tq[t] == pobs) ds.obs_tq = t;
         }
         auto regbit = [&](int p) {
             for (int b = 0; b < rr; ++b)
@@ -633,8 +713,8 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
     out.passes.push_back(dp);
 }
 
-template void encode_pass<float>(const HostPass&, int, int, int, int, int, DevTables<float>&);
-template void encode_pass<double>(const HostPass&, int, int, int, int, int, DevTables<double>&);
+template void encode_pass<float>(const HostPass&, int, int, int, int, int, DevTables<float>&, bool);
+template void encode_pass<double>(const HostPass&, int, int, int, int, int, DevTables<double>&, bool);
 
 std::string describe_plan(const StreamPlan& plan) {
     std::ostringstream os;

@@ -112,9 +112,12 @@ struct DevTables {
     std::vector<DevOp<T>> ops;
 };
 
+// Encodes one pass (or the stages of a one-workgroup plan) into the device
+// tables.  fixed_swizzle: use the one-workgroup kernel's fixed LDS swizzle
+// instead of a layout searched for this pass.
 template <typename T>
 void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, int vec,
-                 DevTables<T>& out);
+                 DevTables<T>& out, bool fixed_swizzle = false);
 
 std::string describe_plan(const StreamPlan& plan);
 
