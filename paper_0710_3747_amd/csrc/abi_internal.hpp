@@ -24,5 +24,6 @@ struct Shape {
     bool valid = true;  // a pass kernel exists for (r, nt)
 };
 Shape choose_shape(int prec, int M, const spin_options* opt);
+void release_batch_caches();
 
 }  // namespace spinqp

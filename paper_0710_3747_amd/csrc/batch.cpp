@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <sstream>
 #include <vector>
 
@@ -94,6 +96,267 @@ static int batch_resident(const spin_problem* probs, int32_t n, const std::vecto
     return SPIN_OK;
 }
 
+
+// ------------------------------------------------------- persistent batch
+struct BatchCache {
+    void *d_probs = nullptr, *d_jobs = nullptr, *d_jstart = nullptr, *d_passes = nullptr,
+         *d_stages = nullptr, *d_ops = nullptr, *d_launch = nullptr, *d_part = nullptr,
+         *d_ctr = nullptr, *d_err = nullptr;
+    int nslots = 0, ncounters = 0;
+    hipStream_t side = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    ~BatchCache() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (side) (void)hipStreamDestroy(side);
+        for (void* p : {d_probs, d_jobs, d_jstart, d_passes, d_stages, d_ops, d_launch, d_part,
+                        d_ctr, d_err})
+            if (p) (void)hipFree(p);
+    }
+};
+
+static std::mutex g_bmu;
+static std::map<std::vector<double>, std::shared_ptr<BatchCache>> g_bcache;
+
+void release_batch_caches() {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    g_bcache.clear();
+}
+
+// Key: everything the tables and the launch depend on.
+static std::vector<double> batch_key(const spin_problem* probs, int n,
+                                     const std::vector<std::vector<Coupling>>& Js, int prec,
+                                     double dt, int64_t n_steps, int init, int dev) {
+    std::vector<double> k{double(prec), dt, double(n_steps), double(init), double(dev), double(n)};
+    for (int p = 0; p < n; ++p) {
+        const spin_problem& pr = probs[p];
+        k.push_back(double(reinterpret_cast<uintptr_t>(pr.psi)));
+        k.push_back(double(reinterpret_cast<uintptr_t>(pr.P_dev)));
+        k.push_back(double(reinterpret_cast<uintptr_t>(pr.N_dev)));
+        k.push_back(pr.M);
+        k.push_back(pr.observed_site);
+        k.push_back(pr.polarized_site);
+        k.push_back(double(pr.seed >> 32));
+        k.push_back(double(pr.seed & 0xffffffffu));
+        for (const Coupling& c : Js[p]) {
+            k.push_back(c.i);
+            k.push_back(c.j);
+            k.push_back(c.a);
+            k.push_back(c.b);
+        }
+    }
+    return k;
+}
+
+template <typename T>
+static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
+                       const std::vector<std::vector<Coupling>>& Js, double dt, int64_t n_steps,
+                       int init, int nslots, BatchCache* bc) {
+    const bool f32 = sizeof(T) == 4;
+    const int K = batch_tile_bits(f32), R = f32 ? 5 : 4, NT = 512, V = f32 ? 2 : 1;
+    DevTables<T> tb;
+    std::vector<BatchProblem> bp;
+    std::vector<int2> launches;
+    std::vector<double> dur;
+    int64_t part = 0;
+    int ncounter = 0;
+    for (int p : sel) {
+        const spin_problem& pr = probs[p];
+        BatchProblem b{};
+        b.psi = pr.psi;
+        b.P = pr.P_dev;
+        b.N = pr.N_dev;
+        b.seed = pr.seed;
+        b.M = pr.M;
+        b.polarized = pr.polarized_site;
+        b.init = init ? 1 : 0;
+        double fops = 0;
+        if (pr.M <= K) {
+            ResidentPlan rp = plan_resident(pr.M, Js[p], dt, pr.observed_site, true, R);
+            const int nthreads = 1 << (pr.M - R);
+            b.gsize = 1;
+            b.pro_stage0 = int(tb.stages.size());
+            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, R, nthreads, 1, tb, true);
+            b.pro_nstage = int(tb.stages.size()) - b.pro_stage0;
+            b.step_stage0 = int(tb.stages.size());
+            encode_pass<T>(rp.step, pr.M, pr.observed_site, R, nthreads, 1, tb, true);
+            b.step_nstage = int(tb.stages.size()) - b.step_stage0;
+            for (const Op& op : rp.step.ops) fops += op.kind == 0;
+            // on-chip: about half the cost per amplitude of a tiled pass
+            dur.push_back(0.5 * fops * std::ldexp(1.0, pr.M) * double(n_steps + 1));
+        } else {
+            PassParams pp;
+            pp.k = K;
+            pp.r = R;
+            pp.c = 3;
+            StreamPlan sp = plan_stream(pr.M, Js[p], dt, n_steps, pr.observed_site, true, pp);
+            b.pass0 = int(tb.passes.size());
+            for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, R, NT, V, tb);
+            b.launch0 = int64_t(launches.size());
+            b.nlaunch = int(sp.launch_tmpl.size());
+            for (size_t l = 0; l < sp.launch_tmpl.size(); ++l)
+                launches.push_back(make_int2(sp.launch_tmpl[l], int(sp.launch_offset[l])));
+            b.ntiles = int64_t(1) << (pr.M - K);
+            b.gsize = int(std::min<int64_t>(b.ntiles, 32));
+            b.part0 = part;
+            part += int64_t(kBatchRing) * b.gsize * 2;
+            b.counter = ncounter++;
+            for (int t : sp.launch_tmpl)
+                for (const Op& op : sp.passes[t].ops) fops += op.kind == 0;
+            // factor work plus one sweep per launch, shared by the gang
+            dur.push_back((fops + 6.0 * sp.launch_tmpl.size()) * std::ldexp(1.0, pr.M) / b.gsize);
+        }
+        bp.push_back(b);
+    }
+    // Gang schedule: slots w with the same w % 8 form an XCD group; longest
+    // jobs first, each onto the group where its gang can start earliest.
+    const int ngroup = nslots >= 8 ? 8 : 1;
+    std::vector<double> avail(nslots, 0.0);
+    std::vector<std::vector<BatchJob>> lists(nslots);
+    std::vector<int> order(bp.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return dur[a] > dur[b]; });
+    for (int q : order) {
+        const int g = bp[q].gsize;
+        double best_start = 1e300;
+        std::vector<int> best;
+        for (int x = 0; x < ngroup; ++x) {
+            std::vector<int> slots;
+            for (int w = x; w < nslots; w += ngroup) slots.push_back(w);
+            if (int(slots.size()) < g) continue;
+            std::stable_sort(slots.begin(), slots.end(), [&](int a, int b) { return avail[a] < avail[b]; });
+            slots.resize(g);
+            double start = 0;
+            for (int w : slots) start = std::max(start, avail[w]);
+            if (start < best_start) {
+                best_start = start;
+                best = slots;
+            }
+        }
+        if (best.empty()) throw std::runtime_error("batch: gang larger than an XCD group");
+        std::sort(best.begin(), best.end());
+        for (int r = 0; r < g; ++r) {
+            lists[best[r]].push_back(BatchJob{q, r});
+            avail[best[r]] = best_start + dur[q];
+        }
+    }
+    std::vector<BatchJob> jobs;
+    std::vector<int> jstart(nslots + 1, 0);
+    for (int w = 0; w < nslots; ++w) {
+        jstart[w] = int(jobs.size());
+        jobs.insert(jobs.end(), lists[w].begin(), lists[w].end());
+    }
+    jstart[nslots] = int(jobs.size());
+
+    auto up = [&](const void* src, size_t n, void** dst) -> int {
+        if (n == 0) n = 16;
+        if (hipMalloc(dst, n) != hipSuccess) return fail(SPIN_ENOMEM, "batch table allocation failed");
+        if (src && hipMemcpy(*dst, src, n, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(SPIN_EHIP, "batch table upload failed");
+        return SPIN_OK;
+    };
+    int rc;
+    if ((rc = up(bp.data(), bp.size() * sizeof(BatchProblem), &bc->d_probs))) return rc;
+    if ((rc = up(jobs.data(), jobs.size() * sizeof(BatchJob), &bc->d_jobs))) return rc;
+    if ((rc = up(jstart.data(), jstart.size() * sizeof(int), &bc->d_jstart))) return rc;
+    if ((rc = up(tb.passes.data(), tb.passes.size() * sizeof(DevPass), &bc->d_passes))) return rc;
+    if ((rc = up(tb.stages.data(), tb.stages.size() * sizeof(DevStage), &bc->d_stages))) return rc;
+    if ((rc = up(tb.ops.data(), tb.ops.size() * sizeof(DevOp<T>), &bc->d_ops))) return rc;
+    if ((rc = up(launches.data(), launches.size() * sizeof(int2), &bc->d_launch))) return rc;
+    if ((rc = up(nullptr, std::max<int64_t>(part, 2) * sizeof(double), &bc->d_part))) return rc;
+    if ((rc = up(nullptr, std::max(ncounter, 1) * sizeof(int), &bc->d_ctr))) return rc;
+    if ((rc = up(nullptr, sizeof(int), &bc->d_err))) return rc;
+    bc->nslots = nslots;
+    bc->ncounters = std::max(ncounter, 1);
+    return SPIN_OK;
+}
+
+template <typename T>
+static int batch_persistent(const spin_problem* probs, const std::vector<int>& sel,
+                            const std::vector<std::vector<Coupling>>& Js, int prec, double dt,
+                            int64_t n_steps, int init, bool use_graph, hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SPIN_EHIP, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(SPIN_EHIP, "device query failed");
+    const int nslots = prop.multiProcessorCount;   // one 512-lane, 128 KiB-LDS workgroup per CU
+
+    // key over the selected problems only
+    std::vector<spin_problem> ps;
+    std::vector<std::vector<Coupling>> js;
+    for (int p : sel) {
+        ps.push_back(probs[p]);
+        js.push_back(Js[p]);
+    }
+    std::vector<double> key = batch_key(ps.data(), int(ps.size()), js, prec, dt, n_steps, init, dev);
+    key.push_back(use_graph ? 1 : 0);
+    std::shared_ptr<BatchCache> bc;
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        auto it = g_bcache.find(key);
+        if (it != g_bcache.end()) bc = it->second;
+    }
+    if (!bc) {
+        bc = std::make_shared<BatchCache>();
+        int rc;
+        try {
+            rc = batch_build<T>(probs, sel, Js, dt, n_steps, init, nslots, bc.get());
+        } catch (const std::exception& e) {
+            return fail(SPIN_EUNSUPPORTED, std::string("batch planning failed: ") + e.what());
+        }
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lk(g_bmu);
+        g_bcache[key] = bc;
+    }
+    auto enqueue = [&](hipStream_t s) {
+        return launch_batch<T>(bc->nslots, static_cast<const BatchProblem*>(bc->d_probs),
+                               static_cast<const BatchJob*>(bc->d_jobs),
+                               static_cast<const int*>(bc->d_jstart),
+                               static_cast<const DevPass*>(bc->d_passes),
+                               static_cast<const DevStage*>(bc->d_stages),
+                               static_cast<const DevOp<T>*>(bc->d_ops),
+                               static_cast<const int2*>(bc->d_launch),
+                               static_cast<double*>(bc->d_part), static_cast<int*>(bc->d_ctr),
+                               bc->ncounters, static_cast<int*>(bc->d_err), n_steps, s);
+    };
+    hipError_t e = hipSuccess;
+    if (use_graph) {
+        // capture on a library stream ordered after the caller's stream
+        if (!bc->side && (e = hipStreamCreateWithFlags(&bc->side, hipStreamNonBlocking)) != hipSuccess)
+            return fail(SPIN_EHIP, std::string("stream: ") + hipGetErrorString(e));
+        if (!bc->exec) {
+            e = hipStreamBeginCapture(bc->side, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) e = enqueue(bc->side);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(bc->side, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&bc->exec, g, nullptr, nullptr, 0);
+            bc->graph = g;
+            if (e != hipSuccess) return fail(SPIN_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return fail(SPIN_EHIP, "event create failed");
+        e = hipEventRecord(ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(bc->side, ev, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(bc->exec, bc->side);
+        if (e == hipSuccess) e = hipEventRecord(ev, bc->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+        if (e == hipSuccess) e = hipStreamSynchronize(bc->side);
+        (void)hipEventDestroy(ev);
+    } else {
+        e = enqueue(st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) return fail(SPIN_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    int err = 0;
+    if ((e = hipMemcpy(&err, bc->d_err, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail(SPIN_EHIP, std::string("batch status: ") + hipGetErrorString(e));
+    if (err) return fail(SPIN_EHIP, "batch: a gang barrier timed out (workgroups not co-resident?)");
+    return SPIN_OK;
+}
+
 }  // namespace spinqp
 
 using namespace spinqp;
@@ -126,12 +389,33 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
                 return fail(SPIN_EINVAL, os.str() + "coupling range outside J_all");
             rc = validate_couplings(pr.M, J_all + pr.coupling_offset, pr.K, &Js[p]);
             if (rc) return fail(rc, os.str() + spin_last_error());
-            if (pr.M > cap) return fail(SPIN_EUNSUPPORTED, os.str() + "M above the one-workgroup capacity");
         }
+        (void)cap;
         if (n == 0) return SPIN_OK;
         hipStream_t st = static_cast<hipStream_t>(stream);
-        int rc = prec == SPIN_C64 ? batch_resident<float>(probs, n, Js, dt, n_steps, init_random_phase, st)
-                                  : batch_resident<double>(probs, n, Js, dt, n_steps, init_random_phase, st);
+        // states smaller than a lane's registers: the grouped one-workgroup
+        // launches; everything else: the persistent launch
+        const int rmin = prec == SPIN_C64 ? 5 : 4;
+        std::vector<int> small, big;
+        for (int p = 0; p < n; ++p) (probs[p].M < rmin ? small : big).push_back(p);
+        int rc = SPIN_OK;
+        if (!small.empty()) {
+            std::vector<spin_problem> sp;
+            std::vector<std::vector<Coupling>> sj;
+            for (int p : small) {
+                sp.push_back(probs[p]);
+                sj.push_back(Js[p]);
+            }
+            rc = prec == SPIN_C64 ? batch_resident<float>(sp.data(), int(sp.size()), sj, dt, n_steps, init_random_phase, st)
+                                  : batch_resident<double>(sp.data(), int(sp.size()), sj, dt, n_steps, init_random_phase, st);
+            if (rc) return rc;
+        }
+        if (!big.empty()) {
+            const bool graph = true;
+            rc = prec == SPIN_C64 ? batch_persistent<float>(probs, big, Js, prec, dt, n_steps, init_random_phase, graph, st)
+                                  : batch_persistent<double>(probs, big, Js, prec, dt, n_steps, init_random_phase, graph, st);
+        }
+        if (rc == SPIN_OK) fail(SPIN_OK, "");
         return rc;
     } catch (const std::exception& e) {
         return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());

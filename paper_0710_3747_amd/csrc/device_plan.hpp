@@ -16,6 +16,7 @@ constexpr int kMaxTileBits = 14;    // 2^14 amplitudes: 128 KiB of complex64 in 
 constexpr int kMaxRegBits = 6;      // at most 64 amplitudes per lane
 constexpr int kMaxMeas = 4;         // observable slots one pass can hold
 constexpr int kMaxSites = 40;
+constexpr int kBatchRing = 16;      // observable slots per gang problem (steps mod 16)
 
 // Op codes.  A two-spin factor on register bits (qa < qb) of a stage has
 // code qa*8 + qb; kOpZZ is or-ed in when the factor carries an I^z I^z

@@ -327,26 +327,25 @@ __device__ __forceinline__ C& lds_at(char* lds, uint32_t byte) {
     return *reinterpret_cast<C*>(lds + byte);
 }
 
-// --------------------------------------------------------------- k_pass
+// ------------------------------------------------------------ tiled pass
+// One pass over the tiles of a group of G workgroups (G a power of two):
+// member w takes the tiles whose index is w' + i*G (w' = w in the group's
+// order), i = 0 .. tiles_per_member-1.  A tile is prefetched into registers
+// while the previous one is worked on in LDS.  Observables accumulate into
+// accP/accN per measurement slot of the pass.
 template <typename T, int R, int NT, bool WRITES>
-__global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi,
-                                             const DevPass* __restrict__ passes,
-                                             const DevStage* __restrict__ stages,
-                                             const DevOp<T>* __restrict__ ops, int pass_index,
-                                             int64_t tiles_per_wg, double* __restrict__ partials,
-                                             int64_t step_offset, int ch, int nwg) {
+__device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, const DevPass& P,
+                                           const DevStage* __restrict__ stages,
+                                           const DevOp<T>* __restrict__ ops, unsigned wperm,
+                                           unsigned G, int64_t tiles_per_member, char* ldsb,
+                                           double (&accP)[kMaxMeas], double (&accN)[kMaxMeas]) {
     using C = typename CT<T>::c;
     using VEC = typename CT<T>::v;
     constexpr int V = CT<T>::V;
     constexpr int K = R + __builtin_ctz(NT);        // tile bits
     constexpr int NIT = (1 << R) / V;               // load/store iterations per lane
     constexpr int EB = sizeof(C);
-    __shared__ C lds[1 << K];
-    __shared__ double red[2 * (NT / 64)];
-
-    const DevPass& P = passes[pass_index];
     const int tid = threadIdx.x;
-    char* ldsb = reinterpret_cast<char*>(lds);
 
     // per-lane load/store offsets: element e = it*NT*V + tid*V (+ v); the
     // iterations walk `it` in Gray-code order
@@ -361,26 +360,12 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
 #pragma unroll
     for (int q = 0; q < 16; ++q) soff_t ^= P.ld_tmask[q] & (0u - ((uint32_t(tid) >> q) & 1u));
 
-    double accP[kMaxMeas], accN[kMaxMeas];
-#pragma unroll
-    for (int m = 0; m < kMaxMeas; ++m) accP[m] = accN[m] = 0.0;
-
-    // Tile bases: tile = blockIdx.x + i * gridDim.x with gridDim.x a power
-    // of two, so base = deposit(blockIdx.x) | (i-th submask of the free
-    // bits above the lowest log2(gridDim.x) ones).
-    // XCD-aware order: workgroups are dispatched round-robin over the 8
-    // XCDs, so w and w + 8 share an L2.  They take adjacent tile indices,
-    // i.e. tiles that differ only in the lowest non-tile address bit and so
-    // share cache lines when the tile's contiguous runs are shorter than a
-    // line.
-    const unsigned G = gridDim.x, w = blockIdx.x;
-    const unsigned wperm = (G >= 8) ? (w % 8u) * (G / 8u) + w / 8u : w;
-    const int64_t base_wg = deposit(wperm, P.free_mask);
+    // Tile bases: tile = wperm + i * G, so base = deposit(wperm) | (i-th
+    // submask of the free bits above the lowest log2(G) ones).
+    const int64_t base_w = deposit(wperm, P.free_mask);
     int64_t m_hi = P.free_mask;
-    for (unsigned g = gridDim.x; g > 1; g >>= 1) m_hi &= m_hi - 1;
+    for (unsigned g = G; g > 1; g >>= 1) m_hi &= m_hi - 1;
 
-    // The next tile is loaded into `pre` while the current one is worked on
-    // in LDS; barriers below only wait for LDS traffic.
     VEC pre[NIT];
     auto prefetch = [&](int64_t base) {
         int64_t g = base + goff_t;
@@ -392,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
         }
     };
     int64_t hi = 0;
-    prefetch(base_wg);
+    prefetch(base_w);
 
     // One tile: prefetched registers -> LDS, stages, LDS -> global.  The
     // next tile's loads are issued right after the LDS fill and are always
@@ -400,10 +385,8 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
     // with the same memory ops outstanding -- prefetch loads, then stores --
     // and the fill only waits for the loads.
     auto tile_body = [&](int64_t it_tile) {
-        const int64_t base = base_wg | hi;
+        const int64_t base = base_w | hi;
         const int tile_sign = P.obs_free_bit >= 0 ? int((base >> P.obs_free_bit) & 1) : 0;
-
-        // prefetched registers -> LDS
         {
             uint32_t a = soff_t;
 #pragma unroll
@@ -424,8 +407,8 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
             }
         }
         lds_barrier();
-        if (it_tile + 1 < tiles_per_wg) hi = next_submask(hi, m_hi);
-        prefetch(base_wg | hi);
+        if (it_tile + 1 < tiles_per_member) hi = next_submask(hi, m_hi);
+        prefetch(base_w | hi);
 
         for (int si = 0; si < P.nstage; ++si) {
             const DevStage& S = stages[P.stage0 + si];
@@ -478,15 +461,51 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
         lds_barrier();
     };
     tile_body(0);
-    for (int64_t it_tile = 1; it_tile < tiles_per_wg; ++it_tile) tile_body(it_tile);
+    for (int64_t it_tile = 1; it_tile < tiles_per_member; ++it_tile) tile_body(it_tile);
+}
 
-    for (int m = 0; m < P.nmeas; ++m) {
-        double p = accP[0], n = accN[0];
+// Workgroup sum of measurement slot m of the accumulators (thread 0).
+template <int NT>
+__device__ __forceinline__ void slot_sum(const double (&accP)[kMaxMeas],
+                                         const double (&accN)[kMaxMeas], int m, double* red,
+                                         double& p, double& n) {
+    p = accP[0];
+    n = accN[0];
 #pragma unroll
-        for (int mm = 1; mm < kMaxMeas; ++mm)
-            if (mm == m) { p = accP[mm]; n = accN[mm]; }
-        block_sum2<NT>(p, n, red);
-        if (tid == 0) {
+    for (int mm = 1; mm < kMaxMeas; ++mm)
+        if (mm == m) { p = accP[mm]; n = accN[mm]; }
+    block_sum2<NT>(p, n, red);
+}
+
+// --------------------------------------------------------------- k_pass
+template <typename T, int R, int NT, bool WRITES>
+__global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi,
+                                             const DevPass* __restrict__ passes,
+                                             const DevStage* __restrict__ stages,
+                                             const DevOp<T>* __restrict__ ops, int pass_index,
+                                             int64_t tiles_per_wg, double* __restrict__ partials,
+                                             int64_t step_offset, int ch, int nwg) {
+    using C = typename CT<T>::c;
+    constexpr int K = R + __builtin_ctz(NT);
+    __shared__ C lds[1 << K];
+    __shared__ double red[2 * (NT / 64)];
+    const DevPass& P = passes[pass_index];
+    double accP[kMaxMeas], accN[kMaxMeas];
+#pragma unroll
+    for (int m = 0; m < kMaxMeas; ++m) accP[m] = accN[m] = 0.0;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8
+    // XCDs, so w and w + 8 share an L2.  They take adjacent tile indices,
+    // i.e. tiles that differ only in the lowest non-tile address bit and so
+    // share cache lines when the tile's contiguous runs are shorter than a
+    // line.
+    const unsigned G = gridDim.x, w = blockIdx.x;
+    const unsigned wperm = (G >= 8) ? (w % 8u) * (G / 8u) + w / 8u : w;
+    pass_tiles<T, R, NT, WRITES>(psi, P, stages, ops, wperm, G, tiles_per_wg,
+                                 reinterpret_cast<char*>(lds), accP, accN);
+    for (int m = 0; m < P.nmeas; ++m) {
+        double p, n;
+        slot_sum<NT>(accP, accN, m, red, p, n);
+        if (threadIdx.x == 0) {
             const int64_t s = step_offset + P.meas_step[m];
             double* dst = partials + ((size_t)(s % ch) * nwg + blockIdx.x) * 2;
             dst[0] = p;
@@ -495,27 +514,21 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
     }
 }
 
-// ------------------------------------------------------------ k_resident
+// ------------------------------------------------------------ resident run
 // One workgroup owns one whole state (2^M <= NT << R amplitudes) in LDS and
-// runs the prologue stages once and the step stages n_steps times,
-// writing P[k], N[k] itself.
+// runs the prologue stages once and the step stages n_steps times, writing
+// P[k], N[k] itself.
 template <typename T, int R, int NT>
-__global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
-                                                 const ResidentJob* __restrict__ jobs,
-                                                 const DevStage* __restrict__ stages,
-                                                 const DevOp<T>* __restrict__ ops,
-                                                 int64_t n_steps) {
+__device__ __forceinline__ void resident_run(const ResidentJob& J, const DevStage* __restrict__ stages,
+                                             const DevOp<T>* __restrict__ ops, int64_t n_steps,
+                                             typename CT<T>::c* lds, double* red) {
     using C = typename CT<T>::c;
     constexpr int EB = sizeof(C);
-    __shared__ C lds[NT << R];
-    __shared__ double red[2 * ((NT + 63) / 64)];
-    const ResidentJob J = jobs ? jobs[blockIdx.x] : job0;
     const int tid = threadIdx.x;
     const int M = J.M;
     const uint32_t dim = 1u << M;
     const int nact = (M >= R) ? (1 << (M - R)) : 1;
     C* psi = reinterpret_cast<C*>(J.psi);
-
     char* ldsb = reinterpret_cast<char*>(lds);
     if (J.init) {
         const double scale = 1.0 / sqrt(ldexp(1.0, M - 1));
@@ -569,6 +582,159 @@ __global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
     for (int64_t k = 1; k <= n_steps; ++k) run(J.step_stage0, J.step_nstage, k);
 
     for (uint32_t x = tid; x < dim; x += NT) psi[x] = lds[lds_swizzle<EB>(x)];
+    __syncthreads();
+}
+
+template <typename T, int R, int NT>
+__global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
+                                                 const ResidentJob* __restrict__ jobs,
+                                                 const DevStage* __restrict__ stages,
+                                                 const DevOp<T>* __restrict__ ops,
+                                                 int64_t n_steps) {
+    using C = typename CT<T>::c;
+    __shared__ C lds[NT << R];
+    __shared__ double red[2 * ((NT + 63) / 64)];
+    const ResidentJob J = jobs ? jobs[blockIdx.x] : job0;
+    resident_run<T, R, NT>(J, stages, ops, n_steps, lds, red);
+}
+
+// ---------------------------------------------------------------- k_batch
+// Persistent batch: each workgroup runs its list of jobs in order.  A job
+// is a whole problem held in LDS (gang size 1, M <= tile bits), or one
+// member's share of a problem run as tiled passes by a gang of G
+// workgroups that meet at a counter after every pass.  The host orders all
+// job lists consistently (a global order of gang start times), so every
+// wait is on members busy with earlier jobs: no cycle, no deadlock.  Each
+// wait is bounded; on time-out the problem is flagged and its P set to NaN.
+// Waits at most kGangWaitTicks of the 100 MHz real-time counter, and gives
+// up at once when any workgroup has flagged an error.
+constexpr uint64_t kGangWaitTicks = 20ull * 100000000ull;   // 20 s
+
+__device__ __forceinline__ bool gang_barrier(int* counter, int target, int* err) {
+    // release: this workgroup's global stores, visible device-wide
+    __threadfence();
+    __syncthreads();
+    __shared__ int ok_s;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        atomicAdd(counter, 1);
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(4);
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                wall_clock64() - t0 > kGangWaitTicks) {
+                atomicOr(err, 1);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();    // acquire
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+template <typename T, int R, int NT>
+__global__ __launch_bounds__(NT) void k_batch(const BatchProblem* __restrict__ probs,
+                                              const BatchJob* __restrict__ jobs,
+                                              const int* __restrict__ job_start,
+                                              const DevPass* __restrict__ passes,
+                                              const DevStage* __restrict__ stages,
+                                              const DevOp<T>* __restrict__ ops,
+                                              const int2* __restrict__ launches,
+                                              double* __restrict__ partials,
+                                              int* __restrict__ counters, int* __restrict__ err,
+                                              int64_t n_steps) {
+    using C = typename CT<T>::c;
+    constexpr int K = R + __builtin_ctz(NT);
+    __shared__ C lds[1 << K];
+    __shared__ double red[2 * (NT / 64)];
+    const int tid = threadIdx.x;
+    for (int jb = job_start[blockIdx.x]; jb < job_start[blockIdx.x + 1]; ++jb) {
+        const BatchJob job = jobs[jb];
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        const BatchProblem& B = probs[job.problem];
+        if (B.gsize == 1 && B.M <= K) {
+            ResidentJob J{};
+            J.psi = B.psi;
+            J.P = B.P;
+            J.N = B.N;
+            J.seed = B.seed;
+            J.M = B.M;
+            J.polarized = B.polarized;
+            J.init = B.init;
+            J.pro_stage0 = B.pro_stage0;
+            J.pro_nstage = B.pro_nstage;
+            J.step_stage0 = B.step_stage0;
+            J.step_nstage = B.step_nstage;
+            resident_run<T, R, NT>(J, stages, ops, n_steps, lds, red);
+            continue;
+        }
+        // gang member `rank` of `gsize`
+        C* psi = reinterpret_cast<C*>(B.psi);
+        const unsigned G = unsigned(B.gsize), rank = unsigned(job.rank);
+        int* ctr = counters + B.counter;
+        int epoch = 0;
+        bool ok = true;
+        if (B.init) {
+            const uint64_t dim = 1ull << B.M;
+            const double scale = 1.0 / sqrt(ldexp(1.0, B.M - 1));
+            for (uint64_t x = uint64_t(rank) * NT + tid; x < dim; x += uint64_t(G) * NT) {
+                double re, im;
+                random_phase_amp(x, B.polarized, B.seed, scale, &re, &im);
+                C c;
+                c.x = T(re);
+                c.y = T(im);
+                psi[x] = c;
+            }
+            ok = gang_barrier(ctr, ++epoch * int(G), err);
+        }
+        const int64_t tpm = B.ntiles / G;
+        for (int l = 0; l < B.nlaunch && ok; ++l) {
+            const int2 la = launches[B.launch0 + l];
+            const DevPass& P = passes[B.pass0 + la.x];
+            double accP[kMaxMeas], accN[kMaxMeas];
+#pragma unroll
+            for (int m = 0; m < kMaxMeas; ++m) accP[m] = accN[m] = 0.0;
+            if (P.writes)
+                pass_tiles<T, R, NT, true>(psi, P, stages, ops, rank, G, tpm,
+                                           reinterpret_cast<char*>(lds), accP, accN);
+            else
+                pass_tiles<T, R, NT, false>(psi, P, stages, ops, rank, G, tpm,
+                                            reinterpret_cast<char*>(lds), accP, accN);
+            for (int m = 0; m < P.nmeas; ++m) {
+                double p, n;
+                slot_sum<NT>(accP, accN, m, red, p, n);
+                if (tid == 0) {
+                    const int64_t s = int64_t(la.y) + P.meas_step[m];
+                    double* dst = partials + B.part0 + ((s % kBatchRing) * G + rank) * 2;
+                    dst[0] = p;
+                    dst[1] = n;
+                }
+            }
+            ok = gang_barrier(ctr, ++epoch * int(G), err);
+            if (rank == 0 && tid == 0 && ok) {
+                for (int m = 0; m < P.nmeas; ++m) {
+                    const int64_t s = int64_t(la.y) + P.meas_step[m];
+                    const double* src = partials + B.part0 + (s % kBatchRing) * G * 2;
+                    double p = 0.0, n = 0.0;
+                    for (unsigned r = 0; r < G; ++r) {
+                        p += src[2 * r];
+                        n += src[2 * r + 1];
+                    }
+                    B.P[s] = p;
+                    if (B.N) B.N[s] = n;
+                }
+            }
+        }
+        if (!ok && rank == 0 && tid == 0)
+            for (int64_t s = 0; s <= n_steps; ++s) B.P[s] = __builtin_nan("");
+    }
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 // ------------------------------------------------------------- launchers
@@ -674,6 +840,35 @@ hipError_t launch_resident(int r, int nt, const ResidentJob& job0, const Residen
     return hipErrorInvalidValue;
 }
 
+int batch_tile_bits(bool f32) { return f32 ? 14 : 13; }
+
+template <typename T>
+hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* jobs,
+                        const int* job_start, const DevPass* passes, const DevStage* stages,
+                        const DevOp<T>* ops, const int2* launches, double* partials, int* counters,
+                        int ncounters, int* err, int64_t n_steps, hipStream_t st) {
+    // counters and the error flag start at zero (a fill kernel, not a
+    // memset node, so the pair can sit in a captured graph)
+    hipLaunchKernelGGL(k_fill_int, dim3(64), dim3(256), 0, st, counters, ncounters, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, err, 1, 0);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_batch<T, 5, 512>), dim3(nslots), dim3(512), 0, st, probs, jobs,
+                           job_start, passes, stages, ops, launches, partials, counters, err,
+                           n_steps);
+    else
+        hipLaunchKernelGGL((k_batch<T, 4, 512>), dim3(nslots), dim3(512), 0, st, probs, jobs,
+                           job_start, passes, stages, ops, launches, partials, counters, err,
+                           n_steps);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch<float>(int, const BatchProblem*, const BatchJob*, const int*,
+                                        const DevPass*, const DevStage*, const DevOp<float>*,
+                                        const int2*, double*, int*, int, int*, int64_t, hipStream_t);
+template hipError_t launch_batch<double>(int, const BatchProblem*, const BatchJob*, const int*,
+                                         const DevPass*, const DevStage*, const DevOp<double>*,
+                                         const int2*, double*, int*, int, int*, int64_t,
+                                         hipStream_t);
 template hipError_t launch_init<float>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_init<double>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_observe<float>(const void*, int, int, double*, int, hipStream_t);

@@ -19,6 +19,25 @@ struct ResidentJob {
     int32_t pad_;
 };
 
+// One problem of a persistent batch launch.
+struct BatchProblem {
+    void* psi;
+    double* P;
+    double* N;
+    uint64_t seed;
+    int32_t M, polarized, init, gsize;   // gsize 1 with M <= tile bits: held in LDS
+    // held in LDS: stage ranges of the prologue and of one step
+    int32_t pro_stage0, pro_nstage, step_stage0, step_nstage;
+    // gang: pass templates, launch list (template, step offset), tiles
+    int32_t pass0, nlaunch;
+    int64_t launch0, ntiles, part0;
+    int32_t counter, pad_;
+};
+
+struct BatchJob {
+    int32_t problem, rank;
+};
+
 struct PassShape {
     int r;    // register bits (amplitudes per lane = 2^r)
     int nt;   // lanes per workgroup; tile bits k = r + log2(nt)
@@ -40,6 +59,14 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
                        const DevStage* stages, const DevOp<T>* ops, int pass_index,
                        int64_t tiles_per_wg, int nwg, double* partials, int64_t step_offset,
                        int ch, hipStream_t st);
+// Persistent batch launch over `nslots` workgroups (all resident at once).
+template <typename T>
+hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* jobs,
+                        const int* job_start, const DevPass* passes, const DevStage* stages,
+                        const DevOp<T>* ops, const int2* launches, double* partials, int* counters,
+                        int ncounters, int* err, int64_t n_steps, hipStream_t st);
+int batch_tile_bits(bool f32);
+
 template <typename T>
 hipError_t launch_resident(int r, int nt, const ResidentJob& job0, const ResidentJob* jobs,
                            int njobs, const DevStage* stages, const DevOp<T>* ops,

@@ -230,3 +230,65 @@ def test_batch_matches_single_runs(prec):
     p = probs[0]
     Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
     assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_gangs_match_single_runs(prec):
+    """Problems larger than one workgroup run as gangs of workgroups inside
+    the persistent launch; states must equal the single-problem path's bit
+    for bit (same plan, same arithmetic) and P agree to FP64 rounding."""
+    import torch
+    Ms = [15, 14, 16, 17, 18, 6, 15]
+    steps, dt = 30, 0.02
+    probs = []
+    for r, M in enumerate(Ms):
+        probs.append(dict(psi=torch.empty(2 ** M, dtype=torch.complex64 if prec == C64 else torch.complex128,
+                                          device="cuda"),
+                          M=M, couplings=workloads.star(M, 300 + r), observed_site=0, polarized_site=0,
+                          seed=700 + r, P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"),
+                          N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
+    note("batch gangs", prec, Ms)
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    torch.cuda.synchronize()
+    for p in probs:
+        P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+        assert np.abs(p["P"].cpu().numpy() - P).max() < 1e-13
+        assert np.array_equal(p["psi"].cpu().numpy().astype(np.complex128), psi)
+    p = probs[0]
+    Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+    assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
+    # a second call with the same problems reuses the cached launch
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    torch.cuda.synchronize()
+    assert np.abs(probs[0]["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
+
+
+def test_batch_config_256_uneven_stars():
+    """256 stars, M uniform in 14..20, couplings as the M = 28 star, 500
+    steps at dt = 0.02, complex64, one persistent launch."""
+    import torch
+    cfg = workloads.BATCH_STARS
+    spec = workloads.star_batch(cfg["n"], cfg["m_lo"], cfg["m_hi"], cfg["size_seed"],
+                                cfg["coupling_seed0"], cfg["state_seed0"])
+    steps, dt = cfg["n_steps"], cfg["dt"]
+    probs = []
+    for p in spec:
+        probs.append(dict(psi=torch.empty(2 ** p["M"], dtype=torch.complex64, device="cuda"),
+                          M=p["M"], couplings=p["couplings"], observed_site=0, polarized_site=0,
+                          seed=p["seed"], P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"),
+                          N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
+    note("batch 256 stars")
+    spq.spin_trotter_evolve_batch(probs, C64, dt, steps, init_random_phase=True)
+    torch.cuda.synchronize()
+    for p in probs:
+        P, N = p["P"].cpu().numpy(), p["N"].cpu().numpy()
+        assert np.isfinite(P).all() and abs(P[0] - 1) < 1e-6
+        assert np.abs(N - 1).max() < 1e-4
+    picks = [int(np.argmin([p["M"] for p in probs])), 7, int(np.argmax([p["M"] for p in probs]))]
+    for i in picks:
+        p = probs[i]
+        P, _, _, _ = gpu_evolve(C64, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"], keep_state=False)
+        assert np.abs(p["P"].cpu().numpy() - P).max() < 1e-12
+    p = probs[picks[0]]     # the oracle on a smallest problem, full run
+    Pw, _, _ = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+    assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[C64]
