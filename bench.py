@@ -86,16 +86,74 @@ def summarize(res, w, steps, prec_bytes):
                 one_sweep_frac=(2 * state_bytes * steps / sec / 1e9) / HBM_PEAK_GBS)
 
 
-def cpu_baseline(w, n_couplings=4):
+def other_workload(name):
+    import workloads
+    if name in ("ladder_2x5", "ladder_2x12", "ladder_2x15"):
+        L, dt, steps, seed = workloads.LADDER_CONFIGS[name]
+        return dict(name=name + "_xy", M=2 * L, J=workloads.ladder(L), dt=dt, steps=steps, seed=seed,
+                    observed=0, polarized=0)
+    if name == "star_28":
+        c = workloads.STAR_M28
+        return dict(name="star_28_xy", M=c["M"], J=workloads.star(c["M"], c["coupling_seed"]),
+                    dt=c["dt"], steps=c["n_steps"], seed=c["seed"], observed=0, polarized=0)
+    raise ValueError(name)
+
+
+def run_batch(spq, torch, reps=2):
+    """256 independent stars (M uniform in 14..20), 500 steps, complex64,
+    one persistent launch (after one untimed call that plans and warms)."""
+    import workloads
+    cfg = workloads.BATCH_STARS
+    spec = workloads.star_batch(cfg["n"], cfg["m_lo"], cfg["m_hi"], cfg["size_seed"],
+                                cfg["coupling_seed0"], cfg["state_seed0"])
+    steps, dt = cfg["n_steps"], cfg["dt"]
+    probs = []
+    for p in spec:
+        probs.append(dict(psi=torch.empty(2 ** p["M"], dtype=torch.complex64, device="cuda"),
+                          M=p["M"], couplings=p["couplings"], observed_site=0, polarized_site=0,
+                          seed=p["seed"], P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"),
+                          N=None))
+    spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init_random_phase=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init_random_phase=True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    upd = sum(2 * len(p["couplings"]) * 2 ** p["M"] * steps for p in spec)
+    return {"workload": "batch_256_stars_M14to20", "steps": steps, "seconds": sec,
+            "amplitude_updates_per_s": upd / sec, "problems": len(spec),
+            "amplitude_updates": upd, "state_bytes": sum(8 * 2 ** p["M"] for p in spec)}
+
+
+def measured_traffic(prec_key):
+    """HBM bytes per pass-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_pass_ladder2x15_M30_traffic.json")
+    src = os.path.join(ROOT, "paper_0710_3747_amd", "csrc")
+    try:
+        t = json.load(open(path))
+        h = hashlib.sha256()
+        for f in ("kernels.hip", "device_plan.hpp"):
+            h.update(open(os.path.join(src, f), "rb").read())
+        if h.hexdigest()[:16] != t["kernel_source_sha256_16"]:
+            return None
+        return t[prec_key]["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, n_couplings=None):
     """The plain C oracle on a bounded sample of the same workload: one
-    Strang step over the first `n_couplings` couplings (2 n_couplings factor
-    applications) of the M = 30 state, complex128, all OpenMP threads."""
+    Strang step (all couplings, 2K factor applications, 2 observables) of
+    the M = 30 state, complex128, all OpenMP threads."""
     import numpy as np
     from oracle import cref
     cref.build(force=False)
     M = w["M"]
     psi = cref.init_random_phase(M, w["polarized"], w["seed"])
-    J = w["J"][:n_couplings]
+    J = w["J"] if n_couplings is None else w["J"][:n_couplings]
     t0 = time.perf_counter()
     cref.trotter_run(psi, M, J, w["dt"], 1, w["observed"])
     sec = time.perf_counter() - t0
@@ -103,8 +161,8 @@ def cpu_baseline(w, n_couplings=4):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     nfac = 2 * len(J)
     return dict(value=nfac * 2 ** M / sec, unit="amplitude-updates/s", cores=threads, kind="oracle",
-                sample=f"{nfac} factor applications (one Strang step of the first {len(J)} couplings) "
-                       f"plus 2 observables on the M={M} complex128 state; {sec:.2f} s",
+                sample=f"one Strang step ({nfac} factor applications of {len(J)} couplings, "
+                       f"2 observables) of the M={M} complex128 state; {sec:.2f} s",
                 seconds=sec)
 
 
@@ -138,6 +196,9 @@ def main():
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--coalesce-bits", type=int, default=0)
+    ap.add_argument("--workload", default="ladder_2x15",
+                    choices=["ladder_2x15", "ladder_2x12", "ladder_2x5", "star_28", "batch_stars"])
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-stars extra")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -154,7 +215,10 @@ def main():
         copy_probe(torch)
         return
     spq.load_library()
-    w = ladder_workload()
+    if args.workload == "batch_stars":
+        print(json.dumps(run_batch(spq, torch)), flush=True)
+        return
+    w = ladder_workload() if args.workload == "ladder_2x15" else other_workload(args.workload)
     steps, warmup = args.steps, args.warmup
 
     opts = None
@@ -190,7 +254,11 @@ def main():
                    "state": "complex64" if res32 is not None else "complex128",
                    "observable": "FP64 P and norm every step"},
         "roofline": {"bound": "hbm", "achieved": s["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": s["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": s["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("c64" if res32 is not None else "c128")
+                     if args.workload == "ladder_2x15" else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, scaled)",
+                     "alg_bytes_per_launch": 2 * 2 ** w["M"] * head_bytes,
                      "kernel": "k_pass", "avg_launch_ms": s["avg_pass_ms"],
                      "launches": s["launches"]},
         "passes_per_step": s["passes_per_step"],
@@ -208,6 +276,11 @@ def main():
         out["err_P_fp32_vs_fp64"] = float(np.abs(res32["P"] - res64["P"]).max())
         out["norm_drift_fp32"] = float(np.abs(res32["N"] - 1).max())
         out["norm_drift_fp64"] = float(np.abs(res64["N"] - 1).max())
+    if args.workload != "ladder_2x15":
+        out["metric"] = "amplitude-updates/s per Trotter step (secondary workload)"
+    elif not args.no_batch:
+        print("[bench] batched stars", file=sys.stderr, flush=True)
+        out["batch_stars"] = run_batch(spq, torch)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(w)
