@@ -164,8 +164,9 @@ static int upload_tables(const DevTables<T>& tb, DevicePlan* dp) {
 // Launch shapes the pass kernel is instantiated for: (register bits, lanes).
 static bool shape_exists(bool f32, int r, int nt) {
     if (f32) return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 5 && nt == 512) ||
-                    (r == 6 && nt == 256);
-    return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 4 && nt == 512);
+                    (r == 6 && nt == 256) || (r == 4 && nt == 512) || (r == 4 && nt == 1024);
+    return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 4 && nt == 512) ||
+           (r == 3 && nt == 512) || (r == 3 && nt == 1024);
 }
 
 // Launch shape: tile bits k = r + log2(nt).  Defaults: complex64 tiles of
@@ -175,7 +176,7 @@ Shape choose_shape(int prec, int M, const spin_options* opt) {
     const bool f32 = prec == SPIN_C64;
     int k = f32 ? 14 : 13;
     s.r = f32 ? 5 : 4;
-    s.c = 3;
+    s.c = f32 ? 5 : 4;   // 256-byte contiguous runs
     if (opt && opt->tile_bits > 0) {
         k = opt->tile_bits;
         s.r = f32 ? (k <= 12 ? 4 : 5) : 4;

@@ -189,7 +189,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             PassParams pp;
             pp.k = K;
             pp.r = R;
-            pp.c = 3;
+            pp.c = sizeof(T) == 4 ? 5 : 4;
             StreamPlan sp = plan_stream(pr.M, Js[p], dt, n_steps, pr.observed_site, true, pp);
             b.pass0 = int(tb.passes.size());
             for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, R, NT, V, tb);

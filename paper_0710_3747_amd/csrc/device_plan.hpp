@@ -46,28 +46,27 @@ struct DevStage {
     int32_t obs_tq;           // thread bit holding the observed site, or -1
     int32_t obs_mask;         // register-index mask of the observed site (0 if none)
     int32_t pad_;
-    uint32_t tmask[16];       // swizzled LDS byte offset of thread bit q (zero past ntb)
-    uint32_t rbit[8];         // swizzled LDS byte offset of register bit q
+    uint32_t tmask[16];       // LDS byte offset of thread bit q (zero past ntb)
+    uint32_t rbit[8];         // LDS byte offset of register bit q
+    // Global element offsets of thread bit q / register bit q, for the first
+    // stage of a pass (loaded straight from HBM, input layout) and the last
+    // (stored straight to HBM, output layout).
+    int64_t gt_in[16], gr_in[8], gt_out[16], gr_out[8];
 };
 
 // One tiled pass over the whole state.
 struct DevPass {
     int32_t k;                // tile bits
-    int32_t stage0, nstage;   // stage range
+    int32_t stage0, nstage;   // stage range (at least one stage)
     int32_t writes;           // 0: read-only pass (observable only)
     int32_t nfree;            // number of non-tile bits
     int32_t obs_free_bit;     // global bit of the observed site if it is not a tile bit, else -1
     int32_t nmeas;            // measurements in this pass
     int32_t pad_;
     int64_t meas_step[kMaxMeas];   // step label of measurement slot m (plus launch offset)
-    int32_t tbit[16];         // global bit of tile-local position p
-    int32_t fbit[kMaxSites];  // global bits not in the tile, increasing (zero-padded)
     int64_t free_mask;        // mask of the global bits not in the tile
-    // load/store iterations: element e = it*NT*V + lane*V; iteration bit b
-    // of `it` sits at tile position log2(NT*V) + b
-    int64_t it_gbit[8];       // global element offset of iteration bit b
-    uint32_t it_lbit[8];      // LDS byte offset of iteration bit b
-    uint32_t ld_tmask[16];    // LDS byte offset of lane bit q in the load/store layout
+    int32_t tbit[16];         // global bit of tile-local position p (input layout)
+    int32_t tbit_out[16];     // global bit of tile-local position p (output layout)
 };
 
 // Fixed LDS swizzle of the one-workgroup kernel (tiled passes use a layout

@@ -330,9 +330,46 @@ __device__ __forceinline__ C& lds_at(char* lds, uint32_t byte) {
 // ------------------------------------------------------------ tiled pass
 // One pass over the tiles of a group of G workgroups (G a power of two):
 // member w takes the tiles whose index is w' + i*G (w' = w in the group's
-// order), i = 0 .. tiles_per_member-1.  A tile is prefetched into registers
-// while the previous one is worked on in LDS.  Observables accumulate into
-// accP/accN per measurement slot of the pass.
+// order), i = 0 .. tiles_per_member-1.  The first register stage of a tile
+// is loaded straight from HBM (lanes along the low address bits, so the
+// wave's accesses are contiguous runs) and the last one stored straight
+// back, in the pass's output layout; the stages in between exchange through
+// LDS.  Every wave has consumed its loads of a tile before the first LDS
+// barrier, so the stores after it cannot overtake another wave's loads.  A
+// one-stage pass never touches LDS and has no such barrier: its lanes store
+// exactly the addresses they loaded (the planner only makes one-stage passes
+// that keep the layout).  The next tile is prefetched into registers while
+// the current one is worked on.  Observables accumulate into accP/accN per
+// measurement slot of the pass.
+template <int R, typename C>
+__device__ __forceinline__ void load_direct(C (&v)[1 << R], const C* __restrict__ psi, int64_t g,
+                                            const int64_t* gr) {
+    v[0] = psi[g];
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) {
+        g ^= gr[__builtin_ctz(i)];
+        v[i ^ (i >> 1)] = psi[g];
+    }
+}
+
+template <int R, typename C>
+__device__ __forceinline__ void store_direct(const C (&v)[1 << R], C* __restrict__ psi, int64_t g,
+                                             const int64_t* gr) {
+    psi[g] = v[0];
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) {
+        g ^= gr[__builtin_ctz(i)];
+        psi[g] = v[i ^ (i >> 1)];
+    }
+}
+
+__device__ __forceinline__ int64_t lane_offset(const int64_t* gt, int tid) {
+    int64_t o = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) o ^= gt[q] & (int64_t(0) - int64_t((uint32_t(tid) >> q) & 1u));
+    return o;
+}
+
 template <typename T, int R, int NT, bool WRITES>
 __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, const DevPass& P,
                                            const DevStage* __restrict__ stages,
@@ -340,25 +377,11 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                                            unsigned G, int64_t tiles_per_member, char* ldsb,
                                            double (&accP)[kMaxMeas], double (&accN)[kMaxMeas]) {
     using C = typename CT<T>::c;
-    using VEC = typename CT<T>::v;
-    constexpr int V = CT<T>::V;
-    constexpr int K = R + __builtin_ctz(NT);        // tile bits
-    constexpr int NIT = (1 << R) / V;               // load/store iterations per lane
-    constexpr int EB = sizeof(C);
     const int tid = threadIdx.x;
-
-    // per-lane load/store offsets: element e = it*NT*V + tid*V (+ v); the
-    // iterations walk `it` in Gray-code order
-    int64_t goff_t = 0;
-    {
-        const uint32_t e = uint32_t(tid) * V;
-#pragma unroll
-        for (int p = 0; p < K; ++p)
-            if (e & (1u << p)) goff_t |= int64_t(1) << P.tbit[p];
-    }
-    uint32_t soff_t = 0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) soff_t ^= P.ld_tmask[q] & (0u - ((uint32_t(tid) >> q) & 1u));
+    const DevStage& S0 = stages[P.stage0];
+    const DevStage& SL = stages[P.stage0 + P.nstage - 1];
+    const int64_t gin_t = lane_offset(S0.gt_in, tid);
+    const int64_t gout_t = lane_offset(SL.gt_out, tid);
 
     // Tile bases: tile = wperm + i * G, so base = deposit(wperm) | (i-th
     // submask of the free bits above the lowest log2(G) ones).
@@ -366,55 +389,27 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
     int64_t m_hi = P.free_mask;
     for (unsigned g = G; g > 1; g >>= 1) m_hi &= m_hi - 1;
 
-    VEC pre[NIT];
-    auto prefetch = [&](int64_t base) {
-        int64_t g = base + goff_t;
-        pre[0] = *reinterpret_cast<const VEC*>(psi + g);
-#pragma unroll
-        for (int i = 1; i < NIT; ++i) {
-            g ^= P.it_gbit[__builtin_ctz(i)];
-            pre[i ^ (i >> 1)] = *reinterpret_cast<const VEC*>(psi + g);
-        }
-    };
+    C pre[1 << R];
     int64_t hi = 0;
-    prefetch(base_w);
+    load_direct<R>(pre, psi, base_w + gin_t, S0.gr_in);
 
-    // One tile: prefetched registers -> LDS, stages, LDS -> global.  The
-    // next tile's loads are issued right after the LDS fill and are always
-    // issued (the last tile re-reads itself) so that every iteration ends
-    // with the same memory ops outstanding -- prefetch loads, then stores --
-    // and the fill only waits for the loads.
+    // One tile.  The next tile's loads are issued at its start and always
+    // (the last tile re-reads itself), so every iteration ends with the same
+    // memory ops outstanding -- prefetch loads, then stores -- and the copy
+    // out of `pre` only waits for the loads.
     auto tile_body = [&](int64_t it_tile) {
         const int64_t base = base_w | hi;
         const int tile_sign = P.obs_free_bit >= 0 ? int((base >> P.obs_free_bit) & 1) : 0;
-        {
-            uint32_t a = soff_t;
+        C v[1 << R];
 #pragma unroll
-            for (int i = 0; i < NIT; ++i) {
-                if (i) a ^= P.it_lbit[__builtin_ctz(i)];
-                const VEC& w = pre[i ^ (i >> 1)];
-                if constexpr (V == 2) {
-                    C lo, hi2;
-                    lo.x = w.x; lo.y = w.y;
-                    hi2.x = w.z; hi2.y = w.w;
-                    lds_at<C>(ldsb, a) = lo;
-                    lds_at<C>(ldsb, a ^ EB) = hi2;
-                } else {
-                    C c;
-                    c.x = w.x; c.y = w.y;
-                    lds_at<C>(ldsb, a) = c;
-                }
-            }
-        }
-        lds_barrier();
+        for (int j = 0; j < (1 << R); ++j) v[j] = pre[j];
         if (it_tile + 1 < tiles_per_member) hi = next_submask(hi, m_hi);
-        prefetch(base_w | hi);
+        load_direct<R>(pre, psi, (base_w | hi) + gin_t, S0.gr_in);
 
         for (int si = 0; si < P.nstage; ++si) {
             const DevStage& S = stages[P.stage0 + si];
             const uint32_t pb = stage_base(S, tid);
-            C v[1 << R];
-            gather<R>(v, ldsb, pb, S);
+            if (si > 0) gather<R>(v, ldsb, pb, S);
             const int sign = tile_sign ^ (S.obs_tq >= 0 ? ((tid >> S.obs_tq) & 1) : 0);
             const int o1 = S.op0 + S.nop;
             int o = S.op0;
@@ -430,35 +425,15 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                     ++o;
                 }
             }
-            // A lane scatters to exactly the LDS slots it gathered, so the
-            // only hazard is with the next stage's gathers (barrier below).
-            scatter<R>(v, ldsb, pb, S);
-            lds_barrier();
-        }
-
-        // LDS -> global (a template switch, not a branch, so the number of
-        // memory ops in flight is the same on every path)
-        if constexpr (WRITES) {
-            uint32_t a = soff_t;
-            int64_t g = base + goff_t;
-#pragma unroll
-            for (int i = 0; i < NIT; ++i) {
-                if (i) {
-                    a ^= P.it_lbit[__builtin_ctz(i)];
-                    g ^= P.it_gbit[__builtin_ctz(i)];
-                }
-                VEC w;
-                if constexpr (V == 2) {
-                    const C lo = lds_at<C>(ldsb, a), hi2 = lds_at<C>(ldsb, a ^ EB);
-                    w.x = lo.x; w.y = lo.y; w.z = hi2.x; w.w = hi2.y;
-                } else {
-                    const C c = lds_at<C>(ldsb, a);
-                    w.x = c.x; w.y = c.y;
-                }
-                *reinterpret_cast<VEC*>(psi + g) = w;
+            if (si + 1 < P.nstage) {
+                // A lane scatters to exactly the LDS slots the next stage's
+                // lanes gather after the barrier.
+                scatter<R>(v, ldsb, pb, S);
+                lds_barrier();
             }
         }
-        lds_barrier();
+        if constexpr (WRITES) store_direct<R>(v, psi, base + gout_t, SL.gr_out);
+        lds_barrier();    // the last gathers are done before the next tile's scatters
     };
     tile_body(0);
     for (int64_t it_tile = 1; it_tile < tiles_per_member; ++it_tile) tile_body(it_tile);
@@ -806,8 +781,9 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
                                     partials, step_offset, ch, st);
     if constexpr (sizeof(T) == 4) {
         SPIN_PASS(5, 256) SPIN_PASS(5, 512) SPIN_PASS(4, 256) SPIN_PASS(6, 256)
+        SPIN_PASS(4, 512) SPIN_PASS(4, 1024)
     } else {
-        SPIN_PASS(4, 256) SPIN_PASS(5, 256) SPIN_PASS(4, 512)
+        SPIN_PASS(4, 256) SPIN_PASS(5, 256) SPIN_PASS(4, 512) SPIN_PASS(3, 512) SPIN_PASS(3, 1024)
     }
 #undef SPIN_PASS
     return hipErrorInvalidValue;

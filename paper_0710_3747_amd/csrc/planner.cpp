@@ -176,11 +176,23 @@ struct Sched {
         return T;
     }
 
+    // The tile the next pass would take with no forced sites (lookahead).
+    // next_pass reuses it when it holds the forced sites.
+    Mask peeked = 0;
+    Mask peek_tile() {
+        peeked = 0;
+        if (all_done()) return 0;
+        limit = ops[first_pending].step + window;
+        peeked = choose_tile(0);
+        return peeked;
+    }
+
     // Schedules one pass; returns the applied op indices (sorted) and T.
     std::vector<int> next_pass(Mask forced, Mask* Tout) {
         all_done();
         limit = ops[first_pending].step + window;
-        Mask T = choose_tile(forced);
+        Mask T = peeked && !(forced & ~peeked) ? peeked : choose_tile(forced);
+        peeked = 0;
         std::vector<int> applied;
         closure(T, &applied);
         if (applied.empty()) throw std::runtime_error("planner: no progress");
@@ -212,6 +224,10 @@ HostPass make_pass(const std::vector<Op>& ops, const std::vector<int>& applied, 
     HostPass hp;
     for (int s = 0; s < M; ++s)
         if (T & bit(s)) hp.sites.push_back(s);
+    hp.bit_in = hp.sites;        // canonical layout: site s is bit s
+    hp.bit_out = hp.sites;
+    hp.layout.resize(M);
+    for (int s = 0; s < M; ++s) hp.layout[s] = s;
     bool any_factor = false;
     for (int n : applied) {
         hp.ops.push_back(ops[n]);
@@ -221,13 +237,164 @@ HostPass make_pass(const std::vector<Op>& ops, const std::vector<int>& applied, 
     return hp;
 }
 
+// Site -> address-bit layout carried from pass to pass.  Every tile keeps
+// the c lowest address bits (contiguous runs of 2^c amplitudes); which
+// sites sit there changes: each pass stores its tile with the sites the
+// next pass will use placed on the low bits (a permutation of the tile's own
+// bits, so the store covers the same addresses it loaded).
+struct Relabel {
+    int M, c;
+    std::vector<int> pi;       // site -> bit
+    Relabel(int M_, int c_) : M(M_), c(c_), pi(M_) {
+        for (int s = 0; s < M; ++s) pi[s] = s;
+    }
+    Mask low_sites() const {
+        Mask m = 0;
+        for (int s = 0; s < M; ++s)
+            if (pi[s] < c) m |= bit(s);
+        return m;
+    }
+    bool identity() const {
+        for (int s = 0; s < M; ++s)
+            if (pi[s] != s) return false;
+        return true;
+    }
+    // Fills the layout fields of hp for tile T (hp.sites set in site order),
+    // choosing the next low-bit sites from T_next, and advances pi.
+    void apply(HostPass& hp, Mask T, Mask T_next) {
+        std::vector<int> sites;
+        for (int s = 0; s < M; ++s)
+            if (T & bit(s)) sites.push_back(s);
+        std::sort(sites.begin(), sites.end(), [&](int a, int b) { return pi[a] < pi[b]; });
+        hp.sites = sites;
+        hp.layout = pi;
+        hp.bit_in.clear();
+        for (int s : sites) hp.bit_in.push_back(pi[s]);
+        // next low-bit sites: in T and in the next tile; keep current ones first
+        const Mask old_low = low_sites();
+        std::vector<int> cand_keep, cand_new, fill;
+        for (int s = 0; s < M; ++s) {
+            if (!(T & bit(s))) continue;
+            const bool nxt = T_next & bit(s), low = old_low & bit(s);
+            if (nxt && low) cand_keep.push_back(s);
+            else if (nxt) cand_new.push_back(s);
+            else fill.push_back(s);
+        }
+        std::vector<int> lows = cand_keep;
+        for (int s : cand_new) lows.push_back(s);
+        // too few shared sites: keep current low sites, then any tile site
+        std::vector<int> rest;
+        for (int s : fill)
+            if (old_low & bit(s)) rest.push_back(s);
+        for (int s : fill)
+            if (!(old_low & bit(s))) rest.push_back(s);
+        for (int s : rest) lows.push_back(s);
+        lows.resize(std::min<size_t>(lows.size(), size_t(c)));
+        // New layout of the tile's bits B: sites staying on the low bits keep
+        // them, entering sites take the freed low bits (both in site order);
+        // every other site returns to its own bit when that bit is in B and
+        // free, the rest fill the remaining bits of B in order.  Pulling
+        // sites home keeps the layout a function of the recent passes, so a
+        // repeating schedule also repeats its layouts.
+        Mask new_low = 0;
+        for (int s : lows) new_low |= bit(s);
+        Mask B = 0;
+        for (int s : sites) B |= bit(pi[s]);
+        Mask used = 0;
+        std::vector<int> npi(pi);
+        std::vector<int> entering;
+        for (int s : sites) {
+            if (!(new_low & bit(s))) continue;
+            if (pi[s] < c) used |= bit(pi[s]);
+            else entering.push_back(s);
+        }
+        int lb = 0;
+        for (int s : entering) {
+            while (used & bit(lb)) ++lb;
+            npi[s] = lb;
+            used |= bit(lb);
+        }
+        std::vector<int> homeless;
+        for (int s : sites) {
+            if (new_low & bit(s)) continue;
+            if (s >= c && (B & bit(s)) && !(used & bit(s))) {
+                npi[s] = s;
+                used |= bit(s);
+            } else {
+                homeless.push_back(s);
+            }
+        }
+        int hb = 0;
+        for (int s : homeless) {
+            while (hb < M && (!(B & bit(hb)) || (used & bit(hb)) || hb < c)) ++hb;
+            if (hb == M) throw std::runtime_error("planner: relabel out of bits");
+            npi[s] = hb;
+            used |= bit(hb);
+        }
+        pi = npi;
+        hp.bit_out.clear();
+        for (int s : sites) hp.bit_out.push_back(pi[s]);
+    }
+    // Layout fields of a pass that keeps the layout (a read-only pass).
+    void keep(HostPass& hp, Mask T) const {
+        std::vector<int> sites;
+        for (int s = 0; s < M; ++s)
+            if (T & bit(s)) sites.push_back(s);
+        std::sort(sites.begin(), sites.end(), [&](int a, int b) { return pi[a] < pi[b]; });
+        hp.sites = sites;
+        hp.layout = pi;
+        hp.bit_in.clear();
+        for (int s : sites) hp.bit_in.push_back(pi[s]);
+        hp.bit_out = hp.bit_in;
+    }
+    // Permutation-only passes (no ops) that bring pi back to the identity.
+    std::vector<HostPass> restore(int k) {
+        std::vector<HostPass> out;
+        for (int guard = 0; !identity() && guard < 4 * M; ++guard) {
+            std::vector<int> pinv(M);
+            for (int s = 0; s < M; ++s) pinv[pi[s]] = s;
+            Mask T = low_sites();
+            for (int s = 0; s < M && popc(T) < k; ++s) {
+                if (pi[s] == s) continue;
+                const Mask need = bit(s) | bit(pinv[s]);
+                if (popc(T | need) <= k) T |= need;
+            }
+            for (int s = 0; s < M && popc(T) < k; ++s) T |= bit(s);
+            HostPass hp;
+            std::vector<int> sites;
+            for (int s = 0; s < M; ++s)
+                if (T & bit(s)) sites.push_back(s);
+            std::sort(sites.begin(), sites.end(), [&](int a, int b) { return pi[a] < pi[b]; });
+            hp.sites = sites;
+            hp.layout = pi;
+            for (int s : sites) hp.bit_in.push_back(pi[s]);
+            // sites whose home bit is in the tile go home; the rest take the
+            // remaining bits in order
+            Mask B = 0;
+            for (int s : sites) B |= bit(pi[s]);
+            std::vector<int> homeless, freebits;
+            Mask taken = 0;
+            for (int s : sites)
+                if (B & bit(s)) taken |= bit(s);
+            for (int s : sites)
+                if (!(B & bit(s))) homeless.push_back(s);
+            for (int s : sites)
+                if (!(taken & bit(pi[s]))) freebits.push_back(pi[s]);
+            std::sort(freebits.begin(), freebits.end());
+            for (int s : sites)
+                if (B & bit(s)) pi[s] = s;
+            for (size_t n = 0; n < homeless.size(); ++n) pi[homeless[n]] = freebits[n];
+            for (int s : sites) hp.bit_out.push_back(pi[s]);
+            hp.writes = true;
+            out.push_back(std::move(hp));
+        }
+        if (!identity()) throw std::runtime_error("planner: layout not restored");
+        return out;
+    }
+};
+
 std::vector<Op> gen_sequence(int M, const std::vector<Coupling>& J, double dt, int observed,
-                             bool merge, int64_t s_begin, int64_t s_end, bool initial_obs,
-                             bool barrier) {
-    // barrier: the observable is made to depend on every site (encoded by
-    // emitting it as an op on each site in turn is not possible), so the
-    // caller asks for no merging and the scheduler treats steps separately.
-    (void)barrier;
+                             bool merge, int64_t s_begin, int64_t s_end, bool initial_obs) {
     SeqBuilder sb(M, J, dt, observed, merge);
     if (initial_obs) sb.emit_observable(0);
     for (int64_t s = s_begin; s <= s_end; ++s) sb.emit_step(s);
@@ -237,7 +404,16 @@ std::vector<Op> gen_sequence(int M, const std::vector<Coupling>& J, double dt, i
 }  // namespace
 
 // ----------------------------------------------------------------- stages
-void plan_stages(HostPass& pass, int r) {
+void plan_stages_coalesced(HostPass& pass, int r, int c) {
+    uint32_t af = 0, al = 0;
+    for (size_t p = 0; p < pass.sites.size(); ++p) {
+        if (pass.bit_in[p] < c) af |= 1u << p;
+        if (pass.bit_out[p] < c) al |= 1u << p;
+    }
+    plan_stages(pass, r, af, al);
+}
+
+void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_last) {
     const int k = int(pass.sites.size());
     const int nops = int(pass.ops.size());
     std::vector<int> local(kMaxSites, -1);
@@ -280,10 +456,13 @@ void plan_stages(HostPass& pass, int r) {
         for (int n = 0; n < nops && int(seeds.size()) < 6; ++n)
             if (!done[n] && ready(n, head) && pass.ops[n].kind == 0) seeds.push_back(n);
         if (seeds.empty()) seeds.push_back(-1);
+        // the first stage's registers may not take the avoided positions
+        const uint32_t avoid = pass.stages.empty() ? avoid_first : 0u;
         for (int seed : seeds) {
             std::vector<int> h = head;
             uint32_t S = 0;
             if (seed >= 0) S = (1u << li[seed]) | (1u << lj[seed]);
+            if (S & avoid) S = 0;
             std::vector<int> got;
             std::vector<char> taken(nops, 0);
             int cnt = 0;
@@ -295,6 +474,7 @@ void plan_stages(HostPass& pass, int r) {
                     const Op& op = pass.ops[n];
                     if (op.kind == 0) {
                         uint32_t need = (1u << li[n]) | (1u << lj[n]);
+                        if (need & avoid) continue;
                         if (__builtin_popcount(S | need) > r) continue;
                         S |= need;
                         ++cnt;
@@ -312,11 +492,17 @@ void plan_stages(HostPass& pass, int r) {
                 best_S = S;
             }
         }
-        if (best_ops.empty()) throw std::runtime_error("planner: stage made no progress");
+        if (best_ops.empty() && !pass.stages.empty())
+            throw std::runtime_error("planner: stage made no progress");
         // Fill the register set up to r positions, highest positions first
-        // (keeps the lanes on low positions: contiguous LDS addresses).
-        for (int p = k - 1; p >= 0 && __builtin_popcount(best_S) < std::min(r, k); --p)
-            best_S |= 1u << p;
+        // (keeps the lanes on low positions), never the avoided ones and
+        // preferably not the last stage's.
+        for (int pass2 = 0; pass2 < 2; ++pass2)
+            for (int p = k - 1; p >= 0 && __builtin_popcount(best_S) < std::min(r, k); --p) {
+                if ((avoid >> p) & 1u) continue;
+                if (pass2 == 0 && ((avoid_last >> p) & 1u)) continue;
+                best_S |= 1u << p;
+            }
         HostStage st;
         for (int p = 0; p < k; ++p)
             if (best_S & (1u << p)) st.regs.push_back(p);
@@ -328,6 +514,29 @@ void plan_stages(HostPass& pass, int r) {
             head[lj[n]] = std::max(head[lj[n]], pj[n] + 1);
         }
         st.ops = best_ops;
+        pass.stages.push_back(std::move(st));
+    }
+    // a pass always has a stage; the last one must be storable directly
+    // A single stage stores from the registers it loaded with no workgroup
+    // barrier in between, so each lane must store exactly the addresses it
+    // loaded (another wave's loads of the tile may still be in flight): only
+    // a pass that keeps its layout can have one stage.
+    auto bad_last = [&]() {
+        if (pass.stages.empty()) return true;
+        uint32_t m = 0;
+        for (int p : pass.stages.back().regs) m |= 1u << p;
+        if (pass.stages.size() == 1)
+            return (m & (avoid_first | avoid_last)) != 0 || pass.bit_in != pass.bit_out;
+        return (m & avoid_last) != 0;
+    };
+    for (int extra = 0; bad_last(); ++extra) {
+        if (extra == 2) throw std::runtime_error("planner: cannot place the last stage");
+        HostStage st;
+        const uint32_t av = pass.stages.empty() ? avoid_first : avoid_last;
+        for (int p = k - 1; p >= 0 && int(st.regs.size()) < std::min(r, k); --p)
+            if (!((av >> p) & 1u)) st.regs.push_back(p);
+        std::sort(st.regs.begin(), st.regs.end());
+        if (int(st.regs.size()) < std::min(r, k)) throw std::runtime_error("planner: tile too small");
         pass.stages.push_back(std::move(st));
     }
 }
@@ -345,6 +554,10 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
     for (int s = 0; s < std::min(pp.c, k); ++s) forced |= bit(s);
     HostPass obs;
     for (int s = 0; s < k; ++s) obs.sites.push_back(s);
+    obs.bit_in = obs.sites;
+    obs.bit_out = obs.sites;
+    obs.layout.resize(M);
+    for (int s = 0; s < M; ++s) obs.layout[s] = s;
     obs.ops.push_back(Op{1, observed, observed, 0, 0, 0, 1 << 30});
     obs.writes = false;
     plan.passes.push_back(obs);
@@ -356,7 +569,7 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
         auto ap = sc.next_pass(forced, &T);
         plan.passes.push_back(make_pass(sb.ops, ap, T, M));
     }
-    for (auto& p : plan.passes) plan_stages(p, std::min(pp.r, int(p.sites.size())));
+    for (auto& p : plan.passes) plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c);
     plan.launch_tmpl.push_back(0);
     plan.launch_offset.push_back(0);
     for (int64_t st = 0; st < n_steps; ++st)
@@ -369,54 +582,98 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
     return plan;
 }
 
-static StreamPlan plan_stream_pipelined(int M, const std::vector<Coupling>& J, double dt,
-                                        int64_t n_steps, int observed, bool merge,
-                                        const PassParams& pp);
+namespace {
 
-StreamPlan plan_stream(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
-                       int observed, bool merge, const PassParams& pp) {
-    try {
-        return plan_stream_pipelined(M, J, dt, n_steps, observed, merge, pp);
-    } catch (const std::runtime_error&) {
-        return plan_stream_per_step(M, J, dt, n_steps, observed, merge, pp);
+// One pass: the tile must hold the sites now on the low bits; a writing pass
+// hands the low bits to sites of the tile the scheduler would take next.
+HostPass schedule_one(Sched& sc, Relabel& rl, const std::vector<Op>& ops, int M) {
+    Mask T;
+    auto ap = sc.next_pass(rl.low_sites(), &T);
+    HostPass hp = make_pass(ops, ap, T, M);
+    if (hp.writes)
+        rl.apply(hp, T, sc.peek_tile());
+    else
+        rl.keep(hp, T);
+    return hp;
+}
+
+// Templates [t0, t0 + n) launched in order with observable labels shifted
+// by `offset`.
+void add_launches(StreamPlan& plan, int t0, int n, int64_t offset) {
+    for (int t = t0; t < t0 + n; ++t) {
+        plan.launch_tmpl.push_back(t);
+        plan.launch_offset.push_back(offset);
     }
 }
 
-static StreamPlan plan_stream_pipelined(int M, const std::vector<Coupling>& J, double dt,
-                                        int64_t n_steps, int observed, bool merge,
-                                        const PassParams& pp) {
+// Appends passes as templates; returns the index of the first.
+int add_templates(StreamPlan& plan, std::vector<HostPass>&& passes) {
+    const int t0 = int(plan.passes.size());
+    for (HostPass& hp : passes) plan.passes.push_back(std::move(hp));
+    return t0;
+}
+
+// Self-contained block: steps 1..n (and the step-0 observable if asked),
+// from the canonical layout back to it.
+std::vector<HostPass> plan_block(int M, const std::vector<Coupling>& J, double dt, int observed,
+                                 bool merge, const PassParams& pp, int64_t n, bool initial_obs) {
+    const int k = std::min(pp.k, M), c = std::min(pp.c, k);
+    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, n, initial_obs);
+    Sched sc(M, observed, k, pp.max_meas, ops);
+    Relabel rl(M, c);
+    std::vector<HostPass> out;
+    while (!sc.all_done()) out.push_back(schedule_one(sc, rl, ops, M));
+    for (HostPass& hp : rl.restore(k)) out.push_back(std::move(hp));
+    return out;
+}
+
+void finish_stages(StreamPlan& plan, const PassParams& pp) {
+    for (auto& p : plan.passes) plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c);
+}
+
+// Blocks of `W` steps repeated verbatim: the first carries the step-0
+// observable, the last the remainder.  Each block drains the pipeline and
+// restores the layout, which costs a few passes per block.
+StreamPlan plan_stream_blocks(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
+                              int observed, bool merge, const PassParams& pp, int64_t W) {
     StreamPlan plan;
     plan.n_steps = n_steps;
-    if (M > 63) throw std::runtime_error("planner: M too large");
-    const int k = std::min(pp.k, M);
-    Mask forced = 0;
-    for (int s = 0; s < std::min(pp.c, k); ++s) forced |= bit(s);
-
-    const int64_t kGen = 48;     // steps generated when searching for a period
-    const int64_t kSafe = 8;     // steps kept between the frontier and the end
-    auto finish = [&](std::vector<HostPass>& passes) {
-        for (auto& p : passes) plan_stages(p, std::min(pp.r, int(p.sites.size())));
-    };
-
-    if (n_steps <= 2 * kGen) {
-        std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, n_steps, true, false);
-        Sched sc(M, observed, k, pp.max_meas, ops);
-        while (!sc.all_done()) {
-            Mask T;
-            auto ap = sc.next_pass(forced, &T);
-            plan.passes.push_back(make_pass(ops, ap, T, M));
-        }
-        finish(plan.passes);
-        for (size_t t = 0; t < plan.passes.size(); ++t) {
-            plan.launch_tmpl.push_back(int(t));
-            plan.launch_offset.push_back(0);
-        }
-        return plan;
+    const int64_t first = std::min(W, n_steps);
+    auto b0 = plan_block(M, J, dt, observed, merge, pp, first, true);
+    const int nb0 = int(b0.size());
+    add_launches(plan, add_templates(plan, std::move(b0)), nb0, 0);
+    const int64_t reps = n_steps / W, rem = n_steps - std::max<int64_t>(reps, 1) * W;
+    if (reps > 1) {
+        auto mid = plan_block(M, J, dt, observed, merge, pp, W, false);
+        const int nm = int(mid.size());
+        const int t0 = add_templates(plan, std::move(mid));
+        for (int64_t r = 1; r < reps; ++r) add_launches(plan, t0, nm, r * W);
+        plan.period_steps = int(W);
+        plan.period_passes = nm;
     }
+    if (rem > 0) {
+        auto last = plan_block(M, J, dt, observed, merge, pp, rem, false);
+        const int nl = int(last.size());
+        add_launches(plan, add_templates(plan, std::move(last)), nl, std::max<int64_t>(reps, 1) * W);
+    }
+    finish_stages(plan, pp);
+    return plan;
+}
 
-    // Long run: schedule the first kGen steps, look for a repeating frontier.
-    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, kGen, true, false);
+// Pipelined long run: schedule kGen steps continuously and look for a
+// repeating state (frontier and layout); the passes between two
+// occurrences are a period template repeated to the end, then a tail.
+StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt,
+                                int64_t n_steps, int observed, bool merge,
+                                const PassParams& pp, int64_t kGen) {
+    StreamPlan plan;
+    plan.n_steps = n_steps;
+    const int k = std::min(pp.k, M);
+    const int c = std::min(pp.c, k);
+    const int64_t kSafe = 8;     // steps kept between the frontier and the end
+    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, kGen, true);
     Sched sc(M, observed, k, pp.max_meas, ops);
+    Relabel rl(M, c);
     std::map<std::vector<int64_t>, std::pair<int, int64_t>> seen;
     std::vector<HostPass> passes;
     int p1 = -1, p2 = -1;
@@ -426,6 +683,7 @@ static StreamPlan plan_stream_pipelined(int M, const std::vector<Coupling>& J, d
     while (!sc.all_done()) {
         if (sc.signature(&sig, &base)) {
             if (base > kGen - kSafe) break;
+            sig.insert(sig.end(), rl.pi.begin(), rl.pi.end());   // the layout is state too
             auto it = seen.find(sig);
             // the merged sequence has period two: only even shifts are exact
             if (it != seen.end() && base > it->second.second &&
@@ -438,9 +696,7 @@ static StreamPlan plan_stream_pipelined(int M, const std::vector<Coupling>& J, d
             }
             if (it == seen.end()) seen[sig] = {int(passes.size()), base};
         }
-        Mask T;
-        auto ap = sc.next_pass(forced, &T);
-        passes.push_back(make_pass(ops, ap, T, M));
+        passes.push_back(schedule_one(sc, rl, ops, M));
     }
     if (p1 < 0) throw std::runtime_error("planner: no periodic schedule found");
     const int64_t delta = s2 - s1;
@@ -480,8 +736,10 @@ static StreamPlan plan_stream_pipelined(int M, const std::vector<Coupling>& J, d
     // regenerate from an odd step so merged ops keep their identities
     int64_t gen_from = std::max<int64_t>(1, base_t - 2);
     if (gen_from % 2 == 0) --gen_from;
-    std::vector<Op> tops = gen_sequence(M, J, dt, observed, merge, gen_from, n_steps, false, false);
+    std::vector<Op> tops = gen_sequence(M, J, dt, observed, merge, gen_from, n_steps, false);
     Sched tc(M, observed, k, pp.max_meas, tops);
+    Relabel tl(M, c);
+    tl.pi.assign(sig1.begin() + 2 * M, sig1.end());
     for (size_t n = 0; n < tops.size(); ++n) {
         const Op& op = tops[n];
         auto before = [&](int s) {
@@ -495,18 +753,37 @@ static StreamPlan plan_stream_pipelined(int M, const std::vector<Coupling>& J, d
         if (d1) tc.mark_done(int(n));
     }
     std::vector<HostPass> tail;
-    while (!tc.all_done()) {
-        Mask T;
-        auto ap = tc.next_pass(forced, &T);
-        tail.push_back(make_pass(tops, ap, T, M));
-    }
-    for (auto& tp : tail) {
-        plan.launch_tmpl.push_back(int(plan.passes.size()));
-        plan.launch_offset.push_back(0);
-        plan.passes.push_back(std::move(tp));
-    }
-    finish(plan.passes);
+    while (!tc.all_done()) tail.push_back(schedule_one(tc, tl, tops, M));
+    for (HostPass& hp : tl.restore(k)) tail.push_back(std::move(hp));
+    const int nt = int(tail.size());
+    add_launches(plan, add_templates(plan, std::move(tail)), nt, 0);
+    finish_stages(plan, pp);
     return plan;
+}
+
+}  // namespace
+
+StreamPlan plan_stream(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
+                       int observed, bool merge, const PassParams& pp) {
+    if (M > 63) throw std::runtime_error("planner: M too large");
+    const int64_t kGen = 48;     // steps scheduled when searching for a period
+    if (n_steps <= 2 * kGen)
+        return plan_stream_blocks(M, J, dt, n_steps, observed, merge, pp, std::max<int64_t>(n_steps, 1));
+    StreamPlan best;
+    bool have = false;
+    try {
+        best = plan_stream_periodic(M, J, dt, n_steps, observed, merge, pp, kGen);
+        have = true;
+    } catch (const std::runtime_error&) {
+    }
+    try {
+        StreamPlan blocks = plan_stream_blocks(M, J, dt, n_steps, observed, merge, pp, kGen);
+        if (!have || blocks.launch_tmpl.size() < best.launch_tmpl.size()) best = std::move(blocks);
+        have = true;
+    } catch (const std::runtime_error&) {
+    }
+    if (have) return best;
+    return plan_stream_per_step(M, J, dt, n_steps, observed, merge, pp);
 }
 
 // --------------------------------------------------------------- resident
@@ -516,6 +793,10 @@ ResidentPlan plan_resident(int M, const std::vector<Coupling>& J, double dt, int
     rp.prologue.sites.resize(M);
     rp.step.sites.resize(M);
     for (int s = 0; s < M; ++s) rp.prologue.sites[s] = rp.step.sites[s] = s;
+    for (HostPass* hp : {&rp.prologue, &rp.step}) {
+        hp->bit_in = hp->bit_out = hp->sites;
+        hp->layout = hp->sites;
+    }
     rp.prologue.ops.push_back(Op{1, observed, observed, 0, 0, 0, 0});
     rp.prologue.writes = false;
     SeqBuilder sb(M, J, dt, observed, merge);
@@ -593,6 +874,9 @@ uint32_t apply_layout(const std::vector<uint32_t>& img, uint32_t l) {
 template <typename T>
 void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, int vec,
                  DevTables<T>& out, bool fixed_swizzle) {
+    (void)r;
+    (void)nthreads;
+    (void)vec;
     const int k = int(hp.sites.size());
     constexpr int eb = sizeof(T) * 2;
     DevPass dp{};
@@ -600,52 +884,52 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
     dp.stage0 = int(out.stages.size());
     dp.nstage = int(hp.stages.size());
     dp.writes = hp.writes ? 1 : 0;
-    int nf = 0;
+    if (hp.stages.empty()) throw std::runtime_error("encode: pass without stages");
     std::vector<int> local(kMaxSites, -1);
+    int64_t tile_bits = 0;
     for (int p = 0; p < k; ++p) {
-        dp.tbit[p] = hp.sites[p];
+        dp.tbit[p] = hp.bit_in[p];
+        dp.tbit_out[p] = hp.bit_out[p];
         local[hp.sites[p]] = p;
+        tile_bits |= int64_t(1) << hp.bit_in[p];
     }
-    for (int s = 0; s < M; ++s)
-        if (local[s] < 0) {
-            dp.fbit[nf++] = s;
-            dp.free_mask |= int64_t(1) << s;
+    int nf = 0;
+    for (int b = 0; b < M; ++b)
+        if (!((tile_bits >> b) & 1)) {
+            dp.free_mask |= int64_t(1) << b;
+            ++nf;
         }
     dp.nfree = nf;
-    dp.obs_free_bit = local[observed] < 0 ? observed : -1;
-    // load/store iterations: element e = it*nthreads*vec + t*vec + v
-    const int per_thread = (1 << k) / nthreads;     // amplitudes per lane
-    const int nit = per_thread / vec;
-    if (nit > 64 || nit < 1 || (nit & (nit - 1))) throw std::runtime_error("encode: bad iteration count");
-    const int lo = __builtin_ctz(unsigned(nthreads * vec));
-    const int vb = __builtin_ctz(unsigned(vec));
+    dp.obs_free_bit = local[observed] < 0 ? hp.layout[observed] : -1;
 
     // thread positions of every stage, and the LDS layout
+    // Thread bit q of a stage is position tq[q].  The lanes of the last stage
+    // of a multi-stage pass take positions in order of output bit, so that
+    // consecutive lanes store consecutive addresses; elsewhere position
+    // order, which is input-bit order.
     std::vector<std::vector<int>> tpos_all;
-    for (const HostStage& hs : hp.stages) {
+    for (size_t si = 0; si < hp.stages.size(); ++si) {
         uint32_t rmask = 0;
-        for (int p : hs.regs) rmask |= 1u << p;
+        for (int p : hp.stages[si].regs) rmask |= 1u << p;
         std::vector<int> tp;
         for (int p = 0; p < k; ++p)
             if (!(rmask & (1u << p))) tp.push_back(p);
+        if (si + 1 == hp.stages.size() && si > 0)
+            std::stable_sort(tp.begin(), tp.end(),
+                             [&](int a, int b) { return hp.bit_out[a] < hp.bit_out[b]; });
         tpos_all.push_back(tp);
     }
+    for (int p = 1; p < k; ++p)
+        if (hp.bit_in[p] <= hp.bit_in[p - 1]) throw std::runtime_error("encode: input bits not increasing");
+    if (hp.stages.size() == 1 && hp.bit_in != hp.bit_out)
+        throw std::runtime_error("encode: one-stage pass that moves amplitudes");
     std::vector<uint32_t> img(k);
     if (fixed_swizzle) {
         for (int p = 0; p < k; ++p) img[p] = lds_swizzle<eb>(1u << p);
     } else {
-        std::vector<std::vector<int>> patterns = tpos_all;
-        std::vector<int> ld;
-        for (int q = 0; vb + q < lo; ++q) ld.push_back(vb + q);
-        patterns.push_back(ld);
-        img = search_layout(k, eb == 8 ? 5 : 4, patterns, uint64_t(k) * 131 + hp.ops.size());
+        img = search_layout(k, eb == 8 ? 5 : 4, tpos_all, uint64_t(k) * 131 + hp.ops.size());
     }
     auto byte_off = [&](uint32_t l) { return apply_layout(img, l) * uint32_t(eb); };
-    for (int b = 0; (1 << b) < nit; ++b) {
-        dp.it_gbit[b] = int64_t(1) << hp.sites[lo + b];
-        dp.it_lbit[b] = byte_off(1u << (lo + b));
-    }
-    for (int q = 0; vb + q < lo && q < 16; ++q) dp.ld_tmask[q] = byte_off(1u << (vb + q));
 
     int nmeas = 0;
     for (size_t si = 0; si < hp.stages.size(); ++si) {
@@ -655,8 +939,16 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
         const int rr = int(hs.regs.size());
         ds.ntb = k - rr;
         const std::vector<int>& tq = tpos_all[si];
-        for (int q = 0; q < ds.ntb; ++q) ds.tmask[q] = byte_off(1u << tq[q]);
-        for (int b = 0; b < rr; ++b) ds.rbit[b] = byte_off(1u << hs.regs[b]);
+        for (int q = 0; q < ds.ntb; ++q) {
+            ds.tmask[q] = byte_off(1u << tq[q]);
+            ds.gt_in[q] = int64_t(1) << hp.bit_in[tq[q]];
+            ds.gt_out[q] = int64_t(1) << hp.bit_out[tq[q]];
+        }
+        for (int b = 0; b < rr; ++b) {
+            ds.rbit[b] = byte_off(1u << hs.regs[b]);
+            ds.gr_in[b] = int64_t(1) << hp.bit_in[hs.regs[b]];
+            ds.gr_out[b] = int64_t(1) << hp.bit_out[hs.regs[b]];
+        }
         ds.obs_tq = -1;
         ds.obs_mask = 0;
         const int pobs = local[observed];

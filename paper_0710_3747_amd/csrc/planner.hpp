@@ -57,7 +57,10 @@ struct HostStage {
 };
 
 struct HostPass {
-    std::vector<int> sites;    // tile-local position p -> site (= global bit)
+    std::vector<int> sites;    // tile-local position p -> site
+    std::vector<int> bit_in;   // tile-local position p -> global bit before the pass (increasing)
+    std::vector<int> bit_out;  // tile-local position p -> global bit after the pass
+    std::vector<int> layout;   // site -> global bit before the pass (all M sites)
     std::vector<Op> ops;       // execution order
     std::vector<HostStage> stages;
     bool writes = true;
@@ -85,9 +88,14 @@ struct StreamPlan {
     }
 };
 
-// Stages for one pass.  `forced_regs_avoid` lists tile-local positions a
-// stage should not use as register bits when it has the choice.
-void plan_stages(HostPass& pass, int r);
+// Stages for one pass.  The first stage is loaded straight from HBM and
+// the last stored straight back, so their register sets must avoid the
+// positions holding the coalescing address bits (avoid_first / avoid_last,
+// masks of tile-local positions); empty stages are added where needed.
+void plan_stages(HostPass& pass, int r, uint32_t avoid_first = 0, uint32_t avoid_last = 0);
+// Same, with the masks taken from the pass's layouts: positions whose input
+// (output) global bit is below c.
+void plan_stages_coalesced(HostPass& pass, int r, int c);
 
 // Full streaming plan: sequence, passes, period search, stages.
 StreamPlan plan_stream(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,

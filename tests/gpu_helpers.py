@@ -41,7 +41,7 @@ def gpu_evolve(prec, M, J, dt, steps, observed, polarized=0, seed=1, opts=None, 
     return P.cpu().numpy(), N.cpu().numpy(), out, psi
 
 
-# tolerances: P from the spec bar; amplitudes relative to the largest
+# tolerances: P absolute (FP64 1e-10, FP32 1e-4); amplitudes relative to the largest
 TOL_P = {spq.SPIN_C128: 1e-10, spq.SPIN_C64: 1e-4}
 TOL_PSI = {spq.SPIN_C128: 1e-10, spq.SPIN_C64: 1e-4}
 
