@@ -169,6 +169,18 @@ int spin_trotter_evolve_batch(const spin_problem *probs, int32_t n, const spin_c
                               int32_t init_random_phase, void *stream);
 
 /*
+ * spin_prepare_plan -- plans the call spin_trotter_evolve_ex would make with
+ * the same arguments (prec, M, J, K, dt, n_steps, observed_site, opt) and
+ * uploads the plan tables to the current device, where they stay cached
+ * until spin_release_caches.  A later evolve call with equal arguments then
+ * does no host planning and no table upload.  No state is touched; the
+ * upload is synchronous.  Errors as spin_trotter_evolve_ex (argument
+ * checks), SPIN_ENOMEM if the tables cannot be allocated.
+ */
+int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
+                      int64_t n_steps, int32_t observed_site, const spin_options *opt);
+
+/*
  * Introspection of the execution plan (host only: no device work, usable
  * without a GPU).  The plan is what spin_trotter_evolve_ex would run for the
  * same arguments.

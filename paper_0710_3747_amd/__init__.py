@@ -92,6 +92,7 @@ def load_library():
     lib.spin_local_polarization.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.spin_trotter_evolve_batch.argtypes = [ctypes.POINTER(Problem), i32, cp, i64, i32, dbl,
                                               i64, i32, vp]
+    lib.spin_prepare_plan.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op]
     lib.spin_describe_plan.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op,
                                        ctypes.POINTER(_PlanInfo)]
     lib.spin_plan_trace.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op,
@@ -101,8 +102,8 @@ def load_library():
     lib.spin_version.restype = ctypes.c_char_p
     lib.spin_release_caches.restype = None
     for name in ("spin_init_random_phase", "spin_trotter_evolve", "spin_trotter_evolve_ex",
-                 "spin_local_polarization", "spin_trotter_evolve_batch", "spin_describe_plan",
-                 "spin_plan_trace"):
+                 "spin_local_polarization", "spin_trotter_evolve_batch", "spin_prepare_plan",
+                 "spin_describe_plan", "spin_plan_trace"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -228,6 +229,16 @@ def spin_trotter_evolve_batch(problems: Sequence[dict], prec: int, dt: float, n_
     _check(lib.spin_trotter_evolve_batch(arr, len(problems), carr, Ktot, prec, float(dt),
                                          int(n_steps), 1 if init_random_phase else 0,
                                          _stream(stream)))
+
+
+def spin_prepare_plan(prec: int, M: int, couplings, dt: float, n_steps: int, observed_site: int,
+                      options: Optional[Options] = None) -> None:
+    """Builds and caches on the current device the plan of the matching
+    evolve call, so that call does no planning or table upload."""
+    lib = load_library()
+    arr, K = _couplings(couplings)
+    _check(lib.spin_prepare_plan(prec, M, arr, K, float(dt), int(n_steps), observed_site,
+                                 ctypes.byref(options) if options is not None else None))
 
 
 def spin_describe_plan(prec: int, M: int, couplings, dt: float, n_steps: int, observed_site: int,

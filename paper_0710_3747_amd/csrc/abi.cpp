@@ -461,6 +461,33 @@ int spin_trotter_evolve_ex(void* psi, int32_t prec, int32_t M, const spin_coupli
     }
 }
 
+int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K, double dt,
+                      int64_t n_steps, int32_t observed_site, const spin_options* opt) {
+    try {
+        if (prec != SPIN_C64 && prec != SPIN_C128) return fail(SPIN_EINVAL, "prec must be SPIN_C64 or SPIN_C128");
+        const int maxM = prec == SPIN_C64 ? SPIN_MAX_M_C64 : SPIN_MAX_M_C128;
+        if (M < 1 || M > maxM) return fail(SPIN_EINVAL, "M out of range");
+        if (!std::isfinite(dt)) return fail(SPIN_EINVAL, "dt is not finite");
+        if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
+        if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
+        if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
+        if (opt && opt->engine != 0) return fail(SPIN_EUNSUPPORTED, "engine option not available");
+        std::vector<Coupling> Jv;
+        int rc = validate_couplings(M, J, K, &Jv);
+        if (rc) return rc;
+        if (opt && opt->schedule == 1) {
+            g_err.clear();
+            return SPIN_OK;     // the unfused schedule has no plan
+        }
+        std::shared_ptr<DevicePlan> dp;
+        rc = get_plan(prec, M, Jv, dt, n_steps, observed_site, opt, &dp, nullptr);
+        if (rc == SPIN_OK) g_err.clear();
+        return rc;
+    } catch (const std::exception& e) {
+        return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());
+    }
+}
+
 int spin_trotter_evolve(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
                         double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
                         double* N_dev, void* stream) {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <stdexcept>
@@ -828,13 +829,18 @@ int gf2_rank(std::vector<uint32_t> v) {
 }
 
 // LDS layout of one tiled pass: element index image of each tile-local
-// position p (phys(l) = xor of img[p] over the set bits of l).  Positions
-// below `nb` (the bank-slot bits: 32 slots of 8 bytes or 16 of 16 bytes in a
-// 256-byte bank row) map to themselves; higher positions also flip a
-// searched set of slot bits.  The search makes every access pattern of the
-// pass -- the load/store layout and each stage's gather -- map the lanes of
-// a 2^nb-lane group onto distinct slots (no bank conflicts).
-std::vector<uint32_t> search_layout(int k, int nb, const std::vector<std::vector<int>>& patterns,
+// position p (phys(l) = xor of img[p] over the set bits of l).  Every
+// position flips its own index bit and a searched set of the nb lowest index
+// bits; the nb x nb block of the lowest positions is kept invertible, so the
+// whole map is.  gfx950 serves an LDS access in groups of lanes: a 64-bit
+// write by 16 lanes at a time, which must hit distinct 8-byte slots modulo
+// 128 bytes, a 64-bit read by 16 lanes (distinct modulo 256 bytes); a
+// 128-bit write by 8 lanes (distinct 16-byte slots modulo 128 bytes) and a
+// 128-bit read by 16 lanes (modulo 256 bytes).  With lane bits on the lowest
+// thread bits, a group is conflict-free when the slot images of its lane
+// bits are linearly independent.  Each stage's scatter (every stage but the
+// last) and gather (every stage but the first) is checked.
+std::vector<uint32_t> search_layout(int k, int elem_bytes, const std::vector<std::vector<int>>& patterns,
                                     uint64_t seed) {
     std::vector<uint32_t> img(k), best;
     int best_def = 1 << 30;
@@ -843,15 +849,40 @@ std::vector<uint32_t> search_layout(int k, int nb, const std::vector<std::vector
         st ^= st << 13; st ^= st >> 7; st ^= st << 17;
         return st;
     };
+    // (lane bits, slot bits) of a write and of a read
+    const std::pair<int, int> wr = elem_bytes == 8 ? std::make_pair(4, 4) : std::make_pair(3, 3);
+    const std::pair<int, int> rd = elem_bytes == 8 ? std::make_pair(4, 5) : std::make_pair(4, 4);
+    const int nb = std::min(k, elem_bytes == 8 ? 5 : 4);
     const uint32_t slot_mask = (1u << nb) - 1;
+    auto deficiency = [&](const std::vector<int>& pat, std::pair<int, int> chk) {
+        std::vector<uint32_t> v;
+        for (int q = 0; q < chk.first && q < int(pat.size()); ++q)
+            v.push_back(img[pat[q]] & ((1u << chk.second) - 1));
+        return int(v.size()) - gf2_rank(v);
+    };
+    // the first stage's lanes (input coalescing) and the last stage's (output
+    // coalescing) are fixed; the lanes of the stages in between are chosen
+    // afterwards (choose_lanes)
+    const int ns = int(patterns.size());
     for (int attempt = 0; attempt < 4000; ++attempt) {
-        for (int p = 0; p < k; ++p)
-            img[p] = (1u << p) | (p >= nb && attempt > 0 ? uint32_t(rnd()) & slot_mask : 0u);
+        // even attempts keep the lowest positions on themselves
+        for (int p = 0; p < k; ++p) {
+            const bool keep = attempt == 0 || (attempt % 2 == 0 && p < nb);
+            img[p] = (1u << p) ^ (keep ? 0u : uint32_t(rnd()) & slot_mask);
+        }
+        std::vector<uint32_t> low(img.begin(), img.begin() + nb);
+        if (gf2_rank(low) < nb) continue;
         int def = 0;
-        for (const auto& pat : patterns) {
-            std::vector<uint32_t> v;
-            for (size_t q = 0; q < pat.size() && int(q) < nb; ++q) v.push_back(img[pat[q]] & slot_mask);
-            def += int(v.size()) - gf2_rank(v);
+        if (ns > 1) def += deficiency(patterns[0], wr) + deficiency(patterns[ns - 1], rd);
+        for (int si = 1; si + 1 < ns; ++si) {
+            // some choice of lanes must satisfy both checks: the thread
+            // positions' slot images must span enough
+            std::vector<uint32_t> w, r;
+            for (int p : patterns[si]) {
+                w.push_back(img[p] & ((1u << wr.second) - 1));
+                r.push_back(img[p] & ((1u << rd.second) - 1));
+            }
+            def += std::max(0, wr.first - gf2_rank(w)) + std::max(0, rd.first - gf2_rank(r));
         }
         if (def < best_def) {
             best_def = def;
@@ -860,6 +891,40 @@ std::vector<uint32_t> search_layout(int k, int nb, const std::vector<std::vector
         }
     }
     return best;
+}
+
+// Orders the thread positions of a stage between the first and the last so
+// that its lowest lane bits take positions whose LDS slot images are
+// independent (conflict-free scatter and gather); the rest keep their order.
+void choose_lanes(std::vector<int>& tp, const std::vector<uint32_t>& img, int elem_bytes) {
+    const int lanes = 4, wbits = elem_bytes == 8 ? 4 : 3, wl = elem_bytes == 8 ? 4 : 3;
+    const int rbits = elem_bytes == 8 ? 5 : 4;
+    if (int(tp.size()) < lanes) return;
+    auto ok = [&](const std::vector<int>& pick) {
+        std::vector<uint32_t> w, r;
+        for (int q = 0; q < int(pick.size()); ++q) {
+            if (q < wl) w.push_back(img[pick[q]] & ((1u << wbits) - 1));
+            r.push_back(img[pick[q]] & ((1u << rbits) - 1));
+        }
+        return gf2_rank(w) == int(w.size()) && gf2_rank(r) == int(r.size());
+    };
+    // depth-first over ordered picks, pruned by the rank conditions
+    std::vector<int> pick, best;
+    std::function<bool()> dfs = [&]() {
+        if (int(pick.size()) == lanes) return true;
+        for (int p : tp) {
+            if (std::find(pick.begin(), pick.end(), p) != pick.end()) continue;
+            pick.push_back(p);
+            if (ok(pick) && dfs()) return true;
+            pick.pop_back();
+        }
+        return false;
+    };
+    if (!dfs()) return;
+    std::vector<int> out = pick;
+    for (int p : tp)
+        if (std::find(pick.begin(), pick.end(), p) == pick.end()) out.push_back(p);
+    tp = out;
 }
 
 uint32_t apply_layout(const std::vector<uint32_t>& img, uint32_t l) {
@@ -927,7 +992,8 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
     if (fixed_swizzle) {
         for (int p = 0; p < k; ++p) img[p] = lds_swizzle<eb>(1u << p);
     } else {
-        img = search_layout(k, eb == 8 ? 5 : 4, tpos_all, uint64_t(k) * 131 + hp.ops.size());
+        img = search_layout(k, eb, tpos_all, uint64_t(k) * 131 + hp.ops.size());
+        for (size_t si = 1; si + 1 < tpos_all.size(); ++si) choose_lanes(tpos_all[si], img, eb);
     }
     auto byte_off = [&](uint32_t l) { return apply_layout(img, l) * uint32_t(eb); };
 
