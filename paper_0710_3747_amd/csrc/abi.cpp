@@ -225,7 +225,7 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             pp.k = sh.k;
             pp.r = sh.r;
             pp.c = sh.c;
-            dp->sp = plan_stream(key.M, J, key.dt, key.n_steps, key.observed, key.merge != 0, pp);
+            dp->sp = plan_stream_best(key.M, J, key.dt, key.n_steps, key.observed, key.merge != 0, pp);
             dp->shape = PassShape{sh.r, sh.nt};
             dp->k = sh.k;
             const int64_t ntiles = int64_t(1) << (key.M - sh.k);
@@ -548,7 +548,7 @@ int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double d
             pp.k = hp->sh.k;
             pp.r = hp->sh.r;
             pp.c = hp->sh.c;
-            hp->sp = plan_stream(M, Jv, dt, n_steps, observed, merge, pp);
+            hp->sp = plan_stream_best(M, Jv, dt, n_steps, observed, merge, pp);
         }
     } catch (const std::exception& e) {
         return fail(SPIN_EUNSUPPORTED, std::string("planning failed: ") + e.what());

@@ -69,6 +69,8 @@ struct Sched {
     int64_t window = 3;
     int64_t limit = INT64_MAX;
 
+    int rotate = 0;    // start offset of the local search's site loops
+
     Sched(int M_, int obs, int k_, int mm, const std::vector<Op>& o)
         : M(M_), observed(obs), k(k_), max_meas(mm), ops(o), site_ops(M_),
           pos_i(o.size()), pos_j(o.size()), head(M_, 0), done(o.size(), 0) {
@@ -158,9 +160,11 @@ struct Sched {
         // First-improvement local search over single-site swaps.
         for (int round = 0; round < 64; ++round) {
             bool improved = false;
-            for (int out = 0; out < M && !improved; ++out) {
+            for (int o2 = 0; o2 < M && !improved; ++o2) {
+                const int out = (o2 + rotate) % M;
                 if (!(T & bit(out)) || (forced & bit(out))) continue;
-                for (int in = 0; in < M; ++in) {
+                for (int i2 = 0; i2 < M; ++i2) {
+                    const int in = (i2 + rotate) % M;
                     if (T & bit(in)) continue;
                     Mask T2 = (T & ~bit(out)) | bit(in);
                     double v = closure(T2, nullptr);
@@ -261,8 +265,10 @@ struct Relabel {
         return true;
     }
     // Fills the layout fields of hp for tile T (hp.sites set in site order),
-    // choosing the next low-bit sites from T_next, and advances pi.
-    void apply(HostPass& hp, Mask T, Mask T_next) {
+    // choosing the next low-bit sites from T_next, preferably outside
+    // `avoid` (the registers of the pass's last stage, which could not be
+    // stored straight to the low bits), and advances pi.
+    void apply(HostPass& hp, Mask T, Mask T_next, Mask avoid, Mask avoid_soft = 0) {
         std::vector<int> sites;
         for (int s = 0; s < M; ++s)
             if (T & bit(s)) sites.push_back(s);
@@ -273,16 +279,20 @@ struct Relabel {
         for (int s : sites) hp.bit_in.push_back(pi[s]);
         // next low-bit sites: in T and in the next tile; keep current ones first
         const Mask old_low = low_sites();
-        std::vector<int> cand_keep, cand_new, fill;
+        std::vector<int> cand_keep, cand_new, cand_soft, cand_avoid, fill;
         for (int s = 0; s < M; ++s) {
             if (!(T & bit(s))) continue;
             const bool nxt = T_next & bit(s), low = old_low & bit(s);
-            if (nxt && low) cand_keep.push_back(s);
+            if (nxt && (avoid & bit(s))) cand_avoid.push_back(s);
+            else if (nxt && (avoid_soft & bit(s))) cand_soft.push_back(s);
+            else if (nxt && low) cand_keep.push_back(s);
             else if (nxt) cand_new.push_back(s);
             else fill.push_back(s);
         }
         std::vector<int> lows = cand_keep;
         for (int s : cand_new) lows.push_back(s);
+        for (int s : cand_soft) lows.push_back(s);
+        for (int s : cand_avoid) lows.push_back(s);
         // too few shared sites: keep current low sites, then any tile site
         std::vector<int> rest;
         for (int s : fill)
@@ -565,6 +575,8 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
     SeqBuilder sb(M, J, dt, observed, merge);
     sb.emit_step(1);
     Sched sc(M, observed, k, pp.max_meas, sb.ops);
+    sc.window = pp.window;
+    sc.rotate = pp.rotate;
     while (!sc.all_done()) {
         Mask T;
         auto ap = sc.next_pass(forced, &T);
@@ -587,14 +599,47 @@ namespace {
 
 // One pass: the tile must hold the sites now on the low bits; a writing pass
 // hands the low bits to sites of the tile the scheduler would take next.
-HostPass schedule_one(Sched& sc, Relabel& rl, const std::vector<Op>& ops, int M) {
+HostPass schedule_one(Sched& sc, Relabel& rl, const std::vector<Op>& ops, int M,
+                      const PassParams& pp) {
     Mask T;
     auto ap = sc.next_pass(rl.low_sites(), &T);
     HostPass hp = make_pass(ops, ap, T, M);
-    if (hp.writes)
-        rl.apply(hp, T, sc.peek_tile());
-    else
+    if (!hp.writes) {
         rl.keep(hp, T);
+        return hp;
+    }
+    // stages with the input layout tell which sites the last stage holds in
+    // registers; the low output bits go preferably to other sites
+    HostPass tmp = hp;
+    rl.keep(tmp, T);
+    uint32_t af = 0;
+    for (size_t p = 0; p < tmp.sites.size(); ++p)
+        if (tmp.bit_in[p] < rl.c) af |= 1u << p;
+    Mask last_regs = 0;
+    try {
+        if (pp.low_policy >= 1) plan_stages(tmp, std::min(pp.r, int(tmp.sites.size())), af, 0);
+        if (pp.low_policy >= 1)
+            for (int q : tmp.stages.back().regs) last_regs |= bit(tmp.sites[q]);
+    } catch (const std::runtime_error&) {
+        last_regs = 0;
+    }
+    // the first stage of the next pass cannot hold low-bit sites in
+    // registers: avoid, if possible, the sites it would start with
+    const Mask T_next = sc.peek_tile();
+    Mask next_first = 0;
+    if (T_next && pp.low_policy >= 2) {
+        std::vector<int> nap;
+        sc.closure(T_next, &nap);
+        HostPass nx = make_pass(ops, nap, T_next, M);
+        rl.keep(nx, T_next);
+        try {
+            plan_stages(nx, std::min(pp.r, int(nx.sites.size())), 0, 0);
+            for (int q : nx.stages.front().regs) next_first |= bit(nx.sites[q]);
+        } catch (const std::runtime_error&) {
+            next_first = 0;
+        }
+    }
+    rl.apply(hp, T, T_next, last_regs, next_first);
     return hp;
 }
 
@@ -621,9 +666,11 @@ std::vector<HostPass> plan_block(int M, const std::vector<Coupling>& J, double d
     const int k = std::min(pp.k, M), c = std::min(pp.c, k);
     std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, n, initial_obs);
     Sched sc(M, observed, k, pp.max_meas, ops);
+    sc.window = pp.window;
+    sc.rotate = pp.rotate;
     Relabel rl(M, c);
     std::vector<HostPass> out;
-    while (!sc.all_done()) out.push_back(schedule_one(sc, rl, ops, M));
+    while (!sc.all_done()) out.push_back(schedule_one(sc, rl, ops, M, pp));
     for (HostPass& hp : rl.restore(k)) out.push_back(std::move(hp));
     return out;
 }
@@ -674,6 +721,8 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
     const int64_t kSafe = 8;     // steps kept between the frontier and the end
     std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, kGen, true);
     Sched sc(M, observed, k, pp.max_meas, ops);
+    sc.window = pp.window;
+    sc.rotate = pp.rotate;
     Relabel rl(M, c);
     std::map<std::vector<int64_t>, std::pair<int, int64_t>> seen;
     std::vector<HostPass> passes;
@@ -697,7 +746,7 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
             }
             if (it == seen.end()) seen[sig] = {int(passes.size()), base};
         }
-        passes.push_back(schedule_one(sc, rl, ops, M));
+        passes.push_back(schedule_one(sc, rl, ops, M, pp));
     }
     if (p1 < 0) throw std::runtime_error("planner: no periodic schedule found");
     const int64_t delta = s2 - s1;
@@ -739,6 +788,8 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
     if (gen_from % 2 == 0) --gen_from;
     std::vector<Op> tops = gen_sequence(M, J, dt, observed, merge, gen_from, n_steps, false);
     Sched tc(M, observed, k, pp.max_meas, tops);
+    tc.window = pp.window;
+    tc.rotate = pp.rotate;
     Relabel tl(M, c);
     tl.pi.assign(sig1.begin() + 2 * M, sig1.end());
     for (size_t n = 0; n < tops.size(); ++n) {
@@ -754,7 +805,7 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
         if (d1) tc.mark_done(int(n));
     }
     std::vector<HostPass> tail;
-    while (!tc.all_done()) tail.push_back(schedule_one(tc, tl, tops, M));
+    while (!tc.all_done()) tail.push_back(schedule_one(tc, tl, tops, M, pp));
     for (HostPass& hp : tl.restore(k)) tail.push_back(std::move(hp));
     const int nt = int(tail.size());
     add_launches(plan, add_templates(plan, std::move(tail)), nt, 0);
@@ -785,6 +836,51 @@ StreamPlan plan_stream(int M, const std::vector<Coupling>& J, double dt, int64_t
     }
     if (have) return best;
     return plan_stream_per_step(M, J, dt, n_steps, observed, merge, pp);
+}
+
+double plan_cost(const StreamPlan& plan, const PlanCostModel& cm) {
+    std::vector<double> tcost(plan.passes.size());
+    for (size_t t = 0; t < plan.passes.size(); ++t) {
+        const HostPass& hp = plan.passes[t];
+        int nf = 0;
+        for (const Op& op : hp.ops) nf += op.kind == 0;
+        tcost[t] = cm.pass + cm.stage * double(hp.stages.size()) + cm.op * nf;
+    }
+    double c = 0;
+    for (int t : plan.launch_tmpl) c += tcost[t];
+    return c;
+}
+
+StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
+                            int observed, bool merge, const PassParams& pp,
+                            const PlanCostModel& cm) {
+    // The schedule reacts strongly to small changes (which sites a tile
+    // keeps, tie-breaks), so variants differ by 10-20 % in cost.  The number
+    // tried grows with the work of the call (amplitude-steps), keeping the
+    // planning time small against the run.
+    std::vector<PassParams> vs;
+    for (int rotate : {0, 3, 6, 9, 12, 15})
+        for (int window : {3, 4})
+            for (int policy : {2, 1}) {
+                PassParams v = pp;
+                v.window = window;
+                v.low_policy = policy;
+                v.rotate = rotate % std::max(M, 1);
+                vs.push_back(v);
+            }
+    const double work = std::ldexp(double(std::max<int64_t>(n_steps, 1)), M);
+    const size_t nv = work < std::ldexp(1.0, 28) ? 1 : work < std::ldexp(1.0, 33) ? 4 : vs.size();
+    StreamPlan best;
+    double best_cost = 0;
+    for (size_t i = 0; i < nv; ++i) {
+        StreamPlan sp = plan_stream(M, J, dt, n_steps, observed, merge, vs[i]);
+        const double c = plan_cost(sp, cm);
+        if (i == 0 || c < best_cost) {
+            best = std::move(sp);
+            best_cost = c;
+        }
+    }
+    return best;
 }
 
 // --------------------------------------------------------------- resident

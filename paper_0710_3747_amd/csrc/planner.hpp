@@ -71,6 +71,19 @@ struct PassParams {
     int r = 5;                 // register bits
     int c = 4;                 // low global bits every tile must contain
     int max_meas = kMaxMeas;
+    // Scheduling variant (plan_stream tries several and keeps the cheapest
+    // by the cost model below):
+    int window = 3;            // steps a pass may run ahead of the oldest pending op
+    int low_policy = 2;        // next low-bit sites avoid: 0 nothing, 1 the last stage's
+                               // registers, 2 also the next pass's first stage
+    int rotate = 0;            // start offset of the tile local search (tie-breaking)
+};
+
+// Modelled cost of a plan in units of one memory-bound pass: a pass costs
+// its sweep plus a share per register stage (an LDS exchange) and per
+// factor op (VALU), fitted to measured pass-kernel durations.
+struct PlanCostModel {
+    double pass = 1.0, stage = 0.26, op = 0.032;
 };
 
 // Plan of one evolve call on the tiled (streaming) path.  Launch l runs
@@ -97,9 +110,19 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first = 0, uint32_t avoid
 // (output) global bit is below c.
 void plan_stages_coalesced(HostPass& pass, int r, int c);
 
-// Full streaming plan: sequence, passes, period search, stages.
+// Full streaming plan for one scheduling variant: sequence, passes, period
+// search, stages.
 StreamPlan plan_stream(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
                        int observed, bool merge, const PassParams& pp);
+
+// Modelled cost of a plan (whole call).
+double plan_cost(const StreamPlan& plan, const PlanCostModel& cm = PlanCostModel());
+
+// Tries a set of scheduling variants of pp and returns the plan of least
+// modelled cost.
+StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
+                            int observed, bool merge, const PassParams& pp,
+                            const PlanCostModel& cm = PlanCostModel());
 
 // Plan for a state that fits one workgroup: stages over all M sites for the
 // prologue (observable of step 0) and for one periodic step (factors, then
