@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--workload", default="ladder_2x15",
                     choices=["ladder_2x15", "ladder_2x12", "ladder_2x5", "star_28", "batch_stars"])
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-stars extra")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default launch shape instead of the autotuner's choice")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -232,12 +234,31 @@ def main():
         opts = spq.Options(tile_bits=args.tile_bits, reg_bits=args.reg_bits,
                            coalesce_bits=args.coalesce_bits)
     res32 = res64 = None
+    tuned = {}
+
+    def shape_for(prec):
+        # explicit shape flags win; otherwise the autotuner's choice (timed
+        # trials before the timed region), unless disabled
+        if opts is not None or args.no_autotune:
+            return opts
+        print(f"[bench] autotuning prec {prec}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        out = spq.spin_autotune(prec, w["M"], w["J"], w["dt"], w["observed"], trial_steps=16)
+        tuned["c64" if prec == spq.SPIN_C64 else "c128"] = {
+            "seconds": time.perf_counter() - t0, "trial_steps": 16,
+            "candidates": [{k: r[k] for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine",
+                                               "ms_per_step", "passes_per_step")} for r in out["results"]],
+            "chosen": {k: getattr(out["best"], k) for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine")}}
+        return out["best"]
+
     if args.prec in ("c64", "both"):
+        o = shape_for(spq.SPIN_C64)
         print(f"[bench] complex64 path, {steps} steps", file=sys.stderr, flush=True)
-        res32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup, opts)
+        res32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup, o)
     if args.prec in ("c128", "both"):
+        o = shape_for(spq.SPIN_C128)
         print(f"[bench] complex128 path, {steps} steps", file=sys.stderr, flush=True)
-        res64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup, opts)
+        res64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup, o)
 
     head = res32 if res32 is not None else res64
     head_bytes = 8 if res32 is not None else 16
@@ -269,6 +290,7 @@ def main():
                      "launches": s["launches"]},
         "passes_per_step": s["passes_per_step"],
         "plan_seconds": head["plan_s"],
+        "shape": {k: head["info"][k] for k in ("tile_bits", "reg_bits", "lanes", "coalesce_bits")},
         "hbm_gbs_per_step": s["hbm_gbs_per_step"],
         "one_sweep_frac": s["one_sweep_frac"],
     }
@@ -283,6 +305,8 @@ def main():
         out["err_P_fp32_vs_fp64"] = float(np.abs(res32["P"] - res64["P"]).max())
         out["norm_drift_fp32"] = float(np.abs(res32["N"] - 1).max())
         out["norm_drift_fp64"] = float(np.abs(res64["N"] - 1).max())
+    if tuned:
+        out["autotune"] = tuned
     if args.workload != "ladder_2x15":
         out["metric"] = "amplitude-updates/s per Trotter step (secondary workload)"
     elif not args.no_batch:

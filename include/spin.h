@@ -59,7 +59,8 @@ typedef enum {
     SPIN_EINVAL = -1,        /* bad argument (range, null pointer, non-finite value) */
     SPIN_ENOMEM = -2,        /* workspace allocation failed */
     SPIN_EHIP = -3,          /* HIP runtime error (message in spin_last_error) */
-    SPIN_EUNSUPPORTED = -4   /* valid request this build cannot serve */
+    SPIN_EUNSUPPORTED = -4,  /* valid request this build cannot serve */
+    SPIN_ENOTFOUND = -5      /* no autotuned entry for these arguments */
 } spin_status;
 
 typedef enum { SPIN_C64 = 1, SPIN_C128 = 2 } spin_prec;
@@ -181,6 +182,46 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
                       int64_t n_steps, int32_t observed_site, const spin_options *opt);
 
 /*
+ * Autotuner (for callers that run the same problem many times, e.g. long or
+ * repeated evolutions).  spin_autotune times trial evolutions of
+ * `trial_steps` steps for a set of launch shapes of the tiled path (tile
+ * bits, register bits, lanes, coalescing bits) and keeps the fastest:
+ *   - key: device architecture and CU count, prec, M, observed_site, dt and
+ *     the coupling list (order and values);
+ *   - the trials run on a scratch state the call allocates (2^M amplitudes)
+ *     and frees; no caller buffer is touched;
+ *   - the call enqueues on `stream` and synchronises it before returning;
+ *   - best: the chosen options (other fields zero), may be NULL;
+ *   - results, cap, n_results: per-candidate outcomes (host array of cap
+ *     records, may be NULL with cap = 0; *n_results = number of candidates);
+ *   - cache_path: if not NULL, a JSON file that receives the choice (created,
+ *     or updated keeping other entries; written atomically by rename).
+ * States small enough for one workgroup have a single shape (one trial).
+ * Planning is done before each timed trial and is not part of the times.
+ * Errors as spin_trotter_evolve_ex; SPIN_ENOMEM if the scratch state cannot
+ * be allocated; SPIN_EUNSUPPORTED if no candidate ran.
+ *
+ * spin_tuned_options returns the stored choice for the same key, from the
+ * process cache or else from cache_path (may be NULL); SPIN_ENOTFOUND if
+ * there is none.  Host only.
+ */
+typedef struct {
+    spin_options opt;        /* the candidate */
+    double ms_per_step;      /* trial time per step, -1 if the candidate failed */
+    double passes_per_step;  /* of the trial's plan */
+    int32_t status;          /* spin_status of the candidate's trial */
+    int32_t reserved_;
+} spin_tune_result;
+
+int spin_autotune(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
+                  int32_t observed_site, int64_t trial_steps, const char *cache_path,
+                  spin_options *best, spin_tune_result *results, int32_t cap,
+                  int32_t *n_results, void *stream);
+
+int spin_tuned_options(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
+                       int32_t observed_site, const char *cache_path, spin_options *best);
+
+/*
  * Introspection of the execution plan (host only: no device work, usable
  * without a GPU).  The plan is what spin_trotter_evolve_ex would run for the
  * same arguments.
@@ -222,8 +263,9 @@ int spin_plan_trace(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *spin_last_error(void);
 
-/* Frees plan caches, captured graphs and workspaces.  Not concurrent-safe
- * with in-flight calls; synchronise the streams used first. */
+/* Frees plan caches, captured graphs, workspaces and the process cache of
+ * autotuned choices (files are kept).  Not concurrent-safe with in-flight
+ * calls; synchronise the streams used first. */
 void spin_release_caches(void);
 
 /* Library version string. */

@@ -24,7 +24,7 @@ __all__ = [
     "Options", "Problem",
 ]
 
-SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EHIP, SPIN_EUNSUPPORTED = 0, -1, -2, -3, -4
+SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EHIP, SPIN_EUNSUPPORTED, SPIN_ENOTFOUND = 0, -1, -2, -3, -4, -5
 SPIN_C64, SPIN_C128 = 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +49,13 @@ class Options(ctypes.Structure):
                 ("reg_bits", ctypes.c_int32), ("coalesce_bits", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("no_merge", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+
+
+class TuneResult(ctypes.Structure):
+    """``spin_tune_result``."""
+    _fields_ = [("opt", Options), ("ms_per_step", ctypes.c_double),
+                ("passes_per_step", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -93,6 +100,9 @@ def load_library():
     lib.spin_trotter_evolve_batch.argtypes = [ctypes.POINTER(Problem), i32, cp, i64, i32, dbl,
                                               i64, i32, vp]
     lib.spin_prepare_plan.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op]
+    lib.spin_autotune.argtypes = [i32, i32, cp, i32, dbl, i32, i64, ctypes.c_char_p, op,
+                                  ctypes.POINTER(TuneResult), i32, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.spin_tuned_options.argtypes = [i32, i32, cp, i32, dbl, i32, ctypes.c_char_p, op]
     lib.spin_describe_plan.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op,
                                        ctypes.POINTER(_PlanInfo)]
     lib.spin_plan_trace.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op,
@@ -103,7 +113,7 @@ def load_library():
     lib.spin_release_caches.restype = None
     for name in ("spin_init_random_phase", "spin_trotter_evolve", "spin_trotter_evolve_ex",
                  "spin_local_polarization", "spin_trotter_evolve_batch", "spin_prepare_plan",
-                 "spin_describe_plan", "spin_plan_trace"):
+                 "spin_describe_plan", "spin_plan_trace", "spin_autotune", "spin_tuned_options"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -239,6 +249,44 @@ def spin_prepare_plan(prec: int, M: int, couplings, dt: float, n_steps: int, obs
     arr, K = _couplings(couplings)
     _check(lib.spin_prepare_plan(prec, M, arr, K, float(dt), int(n_steps), observed_site,
                                  ctypes.byref(options) if options is not None else None))
+
+
+def _opt_dict(o: "Options") -> dict:
+    return {name: getattr(o, name) for name, _ in Options._fields_ if name != "reserved"}
+
+
+def spin_autotune(prec: int, M: int, couplings, dt: float, observed_site: int,
+                  trial_steps: int = 16, cache_path: Optional[str] = None, stream=None) -> dict:
+    """Times the candidate launch shapes on a scratch state (blocking) and
+    returns {"best": Options, "results": [dict per candidate]}."""
+    lib = load_library()
+    arr, K = _couplings(couplings)
+    best = Options()
+    res = (TuneResult * 16)()
+    n = ctypes.c_int32(0)
+    _check(lib.spin_autotune(prec, M, arr, K, float(dt), observed_site, int(trial_steps),
+                             cache_path.encode() if cache_path else None, ctypes.byref(best),
+                             res, 16, ctypes.byref(n), _stream(stream)))
+    out = []
+    for r in res[: min(n.value, 16)]:
+        d = _opt_dict(r.opt)
+        d.update(ms_per_step=r.ms_per_step, passes_per_step=r.passes_per_step, status=r.status)
+        out.append(d)
+    return {"best": best, "results": out}
+
+
+def spin_tuned_options(prec: int, M: int, couplings, dt: float, observed_site: int,
+                       cache_path: Optional[str] = None) -> Optional["Options"]:
+    """The stored autotuned options for these arguments, or None."""
+    lib = load_library()
+    arr, K = _couplings(couplings)
+    best = Options()
+    rc = lib.spin_tuned_options(prec, M, arr, K, float(dt), observed_site,
+                                cache_path.encode() if cache_path else None, ctypes.byref(best))
+    if rc == SPIN_ENOTFOUND:
+        return None
+    _check(rc)
+    return best
 
 
 def spin_describe_plan(prec: int, M: int, couplings, dt: float, n_steps: int, observed_site: int,

@@ -497,6 +497,7 @@ int spin_trotter_evolve(void* psi, int32_t prec, int32_t M, const spin_coupling*
 
 void spin_release_caches(void) {
     release_batch_caches();
+    release_tune_cache();
     std::lock_guard<std::mutex> lk(g_mu);
     g_plans.clear();
     for (auto& kv : g_scratch)

@@ -25,5 +25,6 @@ struct Shape {
 };
 Shape choose_shape(int prec, int M, const spin_options* opt);
 void release_batch_caches();
+void release_tune_cache();
 
 }  // namespace spinqp

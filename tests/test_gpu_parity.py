@@ -292,3 +292,36 @@ def test_batch_config_256_uneven_stars():
     p = probs[picks[0]]     # the oracle on a smallest problem, full run
     Pw, _, _ = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
     assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[C64]
+
+
+def test_autotune_picks_a_shape_stores_it_and_it_evolves_correctly(tmp_path):
+    """The autotuner times every candidate shape, keeps the fastest in the
+    process cache and the JSON file, and the tuned options give the oracle's
+    result."""
+    import json
+    M, J, dt, steps = 18, workloads.ladder(9), 0.05, 12
+    path = str(tmp_path / "tune.json")
+    note("autotune M=18")
+    out = spq.spin_autotune(C64, M, J, dt, 0, trial_steps=6, cache_path=path)
+    res = out["results"]
+    assert len(res) >= 4 and all(r["status"] == 0 and r["ms_per_step"] > 0 for r in res)
+    best = out["best"]
+    fastest = min(res, key=lambda r: r["ms_per_step"])
+    assert (best.tile_bits, best.reg_bits, best.coalesce_bits) == \
+        (fastest["tile_bits"], fastest["reg_bits"], fastest["coalesce_bits"])
+    entries = json.load(open(path))["entries"]
+    assert len(entries) == 1 and list(entries.values())[0]["tile_bits"] == best.tile_bits
+    got = spq.spin_tuned_options(C64, M, J, dt, 0)
+    assert got is not None and got.tile_bits == best.tile_bits
+    spq.spin_release_caches()
+    assert spq.spin_tuned_options(C64, M, J, dt, 0) is None
+    got = spq.spin_tuned_options(C64, M, J, dt, 0, cache_path=path)
+    assert got is not None and (got.tile_bits, got.reg_bits) == (best.tile_bits, best.reg_bits)
+    assert spq.spin_tuned_options(C64, M, J, 2 * dt, 0, cache_path=path) is None
+    P, N, psi, _ = gpu_evolve(C64, M, J, dt, steps, 0, seed=3,
+                              opts={"tile_bits": got.tile_bits, "reg_bits": got.reg_bits,
+                                    "coalesce_bits": got.coalesce_bits})
+    psi0 = oracle.random_phase_state(M, 0, 3)
+    Pw, Nw, psiw = oracle.trotter_run(psi0, M, J, dt, steps, 0)
+    assert np.abs(P - Pw).max() < TOL_P[C64]
+    assert_state_close(psi, psiw, C64)
