@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-stars extra")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default launch shape instead of the autotuner's choice")
+    ap.add_argument("--engine-steps", type=int, default=100,
+                    help="steps of the MFMA-matrix vs VALU-butterfly comparison (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -307,6 +309,23 @@ def main():
         out["norm_drift_fp64"] = float(np.abs(res64["N"] - 1).max())
     if tuned:
         out["autotune"] = tuned
+    if args.workload == "ladder_2x15" and res32 is not None and args.engine_steps > 0:
+        # stage arithmetic on FP32 MFMA (each stage's factors as one dense
+        # 32 x 32 complex matrix) against the VALU butterflies, same shape
+        import numpy as np
+        n = min(args.engine_steps, steps)
+        base = dict(tile_bits=14, reg_bits=5, coalesce_bits=5)
+        print(f"[bench] engine comparison, {n} steps", file=sys.stderr, flush=True)
+        rb = run_path(spq, torch, w, spq.SPIN_C64, n, 2, spq.Options(**base))
+        rm = run_path(spq, torch, w, spq.SPIN_C64, n, 2, spq.Options(engine=1, **base))
+        cmp = {"steps": n, "shape": base,
+               "butterfly_ms_per_step": rb["ms_total"] / n, "mfma_ms_per_step": rm["ms_total"] / n,
+               "mfma_time_ratio": rm["ms_total"] / rb["ms_total"],
+               "passes_per_step": rm["info"]["passes_per_step"],
+               "max_dP_mfma_vs_butterfly": float(np.abs(rm["P"] - rb["P"]).max())}
+        if res64 is not None:
+            cmp["max_dP_mfma_vs_fp64"] = float(np.abs(rm["P"] - res64["P"][: n + 1]).max())
+        out["engine_comparison"] = cmp
     if args.workload != "ladder_2x15":
         out["metric"] = "amplitude-updates/s per Trotter step (secondary workload)"
     elif not args.no_batch:

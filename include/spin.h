@@ -118,7 +118,10 @@ typedef struct {
     int32_t tile_bits;    /* k of the 2^k-amplitude tiles; 0 = autotuned / default */
     int32_t reg_bits;     /* amplitudes per lane = 2^reg_bits; 0 = default */
     int32_t coalesce_bits;/* low address bits every tile keeps; 0 = default */
-    int32_t engine;       /* 0 = VALU butterflies (default); 1 = FP32 MFMA block stages */
+    int32_t engine;       /* 0 = VALU butterflies (default); 1 = each register stage's
+                             factors as one dense 32 x 32 complex matrix on FP32 MFMA
+                             (complex64, tile_bits 14, reg_bits 5; tiled path only:
+                             states held by one workgroup ignore it) */
     int32_t no_merge;     /* 1 = do not merge adjacent same-pair factors */
     int32_t use_graph;    /* 1 = launch through a captured hipGraph */
     int32_t reserved[9];
@@ -185,7 +188,8 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  * Autotuner (for callers that run the same problem many times, e.g. long or
  * repeated evolutions).  spin_autotune times trial evolutions of
  * `trial_steps` steps for a set of launch shapes of the tiled path (tile
- * bits, register bits, lanes, coalescing bits) and keeps the fastest:
+ * bits, register bits, lanes, coalescing bits; complex64 also the MFMA
+ * matrix engine) and keeps the fastest:
  *   - key: device architecture and CU count, prec, M, observed_site, dt and
  *     the coupling list (order and values);
  *   - the trials run on a scratch state the call allocates (2^M amplitudes)
@@ -236,7 +240,7 @@ typedef struct {
     int32_t templates;      /* distinct pass templates (path 2) */
     int32_t period_steps, period_passes;  /* repeating block of the plan (path 2) */
     int32_t stages_total;   /* register stages over all templates */
-    int32_t reserved_;
+    int32_t engine;         /* stage arithmetic of path 2: 0 VALU butterflies, 1 MFMA matrices */
     int64_t launches;       /* pass-kernel launches for the whole call */
     int64_t factor_ops;     /* two-spin factor applications after merging, whole call */
     double passes_per_step; /* launches / n_steps (path 2) */

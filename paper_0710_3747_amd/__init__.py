@@ -71,7 +71,7 @@ class _PlanInfo(ctypes.Structure):
                 ("reg_bits", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("coalesce_bits", ctypes.c_int32), ("templates", ctypes.c_int32),
                 ("period_steps", ctypes.c_int32), ("period_passes", ctypes.c_int32),
-                ("stages_total", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("stages_total", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("launches", ctypes.c_int64), ("factor_ops", ctypes.c_int64),
                 ("passes_per_step", ctypes.c_double)]
 

@@ -110,14 +110,14 @@ int scratch_get(hipStream_t st, size_t bytes, void** out) {
 
 // ------------------------------------------------------------- plan cache
 struct PlanKey {
-    int dev, prec, M, observed, k, r, nt, c, merge;
+    int dev, prec, M, observed, k, r, nt, c, merge, engine;
     double dt;
     int64_t n_steps;
     std::vector<double> J;    // flattened couplings
     bool operator<(const PlanKey& o) const {
-        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, dt, n_steps, J) <
-               std::tie(o.dev, o.prec, o.M, o.observed, o.k, o.r, o.nt, o.c, o.merge, o.dt,
-                        o.n_steps, o.J);
+        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, engine, dt, n_steps, J) <
+               std::tie(o.dev, o.prec, o.M, o.observed, o.k, o.r, o.nt, o.c, o.merge, o.engine,
+                        o.dt, o.n_steps, o.J);
     }
 };
 
@@ -131,6 +131,7 @@ struct DevicePlan {
     void* d_passes = nullptr;
     void* d_stages = nullptr;
     void* d_ops = nullptr;
+    void* d_mats = nullptr;     // matrix engine
     // resident
     int res_r = 0, res_nt = 0;
     int pro_stage0 = 0, pro_nstage = 0, step_stage0 = 0, step_nstage = 0;
@@ -141,6 +142,7 @@ struct DevicePlan {
         if (d_passes) (void)hipFree(d_passes);
         if (d_stages) (void)hipFree(d_stages);
         if (d_ops) (void)hipFree(d_ops);
+        if (d_mats) (void)hipFree(d_mats);
     }
 };
 
@@ -158,15 +160,8 @@ static int upload_tables(const DevTables<T>& tb, DevicePlan* dp) {
     if ((rc = up(tb.passes.data(), tb.passes.size() * sizeof(DevPass), &dp->d_passes))) return rc;
     if ((rc = up(tb.stages.data(), tb.stages.size() * sizeof(DevStage), &dp->d_stages))) return rc;
     if ((rc = up(tb.ops.data(), tb.ops.size() * sizeof(DevOp<T>), &dp->d_ops))) return rc;
+    if (!tb.mats.empty() && (rc = up(tb.mats.data(), tb.mats.size() * sizeof(float), &dp->d_mats))) return rc;
     return SPIN_OK;
-}
-
-// Launch shapes the pass kernel is instantiated for: (register bits, lanes).
-static bool shape_exists(bool f32, int r, int nt) {
-    if (f32) return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 5 && nt == 512) ||
-                    (r == 6 && nt == 256) || (r == 4 && nt == 512) || (r == 4 && nt == 1024);
-    return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 4 && nt == 512) ||
-           (r == 3 && nt == 512) || (r == 3 && nt == 1024);
 }
 
 // Launch shape: tile bits k = r + log2(nt).  Defaults: complex64 tiles of
@@ -186,7 +181,8 @@ Shape choose_shape(int prec, int M, const spin_options* opt) {
     if (f32 && s.c < 1) s.c = 1;     // two-amplitude vector accesses need bit 0
     s.nt = (k - s.r >= 0 && k - s.r < 16) ? (1 << (k - s.r)) : 0;
     s.k = k;
-    s.valid = shape_exists(f32, s.r, s.nt);
+    s.engine = opt ? opt->engine : 0;
+    s.valid = pass_shape_exists(f32, s.r, s.nt, s.engine);
     s.res_cap = f32 ? 14 : 13;
     s.resident = M <= s.res_cap;
     return s;
@@ -214,10 +210,10 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             ResidentPlan rp = plan_resident(key.M, J, key.dt, key.observed, key.merge != 0, dp->res_r);
             const int nthreads = 1 << std::max(0, key.M - dp->res_r);
             dp->pro_stage0 = 0;
-            encode_pass<T>(rp.prologue, key.M, key.observed, dp->res_r, nthreads, 1, tb, true);
+            encode_pass<T>(rp.prologue, key.M, key.observed, tb, true);
             dp->pro_nstage = int(tb.stages.size());
             dp->step_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.step, key.M, key.observed, dp->res_r, nthreads, 1, tb, true);
+            encode_pass<T>(rp.step, key.M, key.observed, tb, true);
             dp->step_nstage = int(tb.stages.size()) - dp->step_stage0;
             dp->stages_total = tb.stages.size();
         } else {
@@ -227,6 +223,7 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             pp.c = sh.c;
             dp->sp = plan_stream_best(key.M, J, key.dt, key.n_steps, key.observed, key.merge != 0, pp);
             dp->shape = PassShape{sh.r, sh.nt};
+            dp->shape.engine = sh.engine;
             dp->k = sh.k;
             const int64_t ntiles = int64_t(1) << (key.M - sh.k);
             int dev_cu = 256;
@@ -239,9 +236,8 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             while (nwg * 2 <= ntiles && nwg * 2 <= int64_t(dev_cu) * 4) nwg *= 2;
             dp->nwg = int(nwg);
             dp->tiles_per_wg = ntiles / nwg;
-            const int vec = sizeof(T) == 4 ? 2 : 1;
             for (const HostPass& hp : dp->sp.passes) {
-                encode_pass<T>(hp, key.M, key.observed, sh.r, sh.nt, vec, tb);
+                encode_pass<T>(hp, key.M, key.observed, tb, false, sh.engine);
                 std::vector<int64_t> ms;
                 for (const Op& op : hp.ops)
                     if (op.kind == 1) ms.push_back(op.step);
@@ -266,11 +262,12 @@ int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t
     Shape sh = choose_shape(prec, M, opt);
     if (!sh.resident && !sh.valid) {
         std::ostringstream os;
-        os << "no pass kernel for tile_bits " << sh.k << " with reg_bits " << sh.r;
+        os << "no pass kernel for tile_bits " << sh.k << " with reg_bits " << sh.r
+           << (sh.engine ? " and the matrix engine (complex64, tile_bits 14, reg_bits 5 only)" : "");
         return fail(SPIN_EUNSUPPORTED, os.str());
     }
     PlanKey key{dev, prec, M, observed, sh.k, sh.r, sh.nt, sh.c,
-                (opt && opt->no_merge) ? 0 : 1, dt, sh.resident ? 0 : n_steps, {}};
+                (opt && opt->no_merge) ? 0 : 1, sh.resident ? 0 : sh.engine, dt, sh.resident ? 0 : n_steps, {}};
     key.J.reserve(J.size() * 4);
     for (const Coupling& c : J) {
         key.J.push_back(c.i);
@@ -369,6 +366,7 @@ static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double
         const int t = dp->sp.launch_tmpl[l];
         const int64_t off = dp->sp.launch_offset[l];
         PassShape shp = dp->shape;
+        shp.mats = static_cast<const float*>(dp->d_mats);
         shp.writes = dp->sp.passes[t].writes;
         HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp->d_passes),
                                 static_cast<const DevStage*>(dp->d_stages),
@@ -441,7 +439,7 @@ int spin_trotter_evolve_ex(void* psi, int32_t prec, int32_t M, const spin_coupli
         if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
         if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
         if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
-        if (opt && opt->engine != 0) return fail(SPIN_EUNSUPPORTED, "engine option not available");
+        if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
         std::vector<Coupling> Jv;
         if ((rc = validate_couplings(M, J, K, &Jv))) return rc;
         hipStream_t st = static_cast<hipStream_t>(stream);
@@ -471,7 +469,7 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K
         if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
         if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
         if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
-        if (opt && opt->engine != 0) return fail(SPIN_EUNSUPPORTED, "engine option not available");
+        if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
         std::vector<Coupling> Jv;
         int rc = validate_couplings(M, J, K, &Jv);
         if (rc) return rc;
@@ -531,6 +529,8 @@ struct HostPlan {
 
 int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double dt, int64_t n_steps,
               int32_t observed, const spin_options* opt, HostPlan* hp) {
+    if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
+    if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
     hp->sh = choose_shape(prec, M, opt);
     if (!(opt && opt->schedule == 1) && !hp->sh.resident && !hp->sh.valid)
         return fail(SPIN_EUNSUPPORTED, "no pass kernel for the requested tile shape");
@@ -587,6 +587,7 @@ extern "C" int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling* 
         info->reg_bits = hp.sh.r;
         info->lanes = hp.sh.nt;
         info->coalesce_bits = hp.sh.c;
+        info->engine = hp.sh.engine;
         info->templates = int(hp.sp.passes.size());
         info->period_steps = hp.sp.period_steps;
         info->period_passes = hp.sp.period_passes;

@@ -20,8 +20,9 @@ struct Shape {
     int k = 14;         // tile bits = r + log2(nt)
     int c = 3;          // low address bits every tile keeps (coalescing)
     int res_cap = 14;   // largest M held by one workgroup
+    int engine = 0;     // 0: VALU butterflies, 1: MFMA stage matrices
     bool resident = false;
-    bool valid = true;  // a pass kernel exists for (r, nt)
+    bool valid = true;  // a pass kernel exists for (r, nt, engine)
 };
 Shape choose_shape(int prec, int M, const spin_options* opt);
 void release_batch_caches();

@@ -1,5 +1,6 @@
 // autotune.cpp -- picks the launch shape of the tiled path (tile bits k,
-// register bits, lanes, coalescing bits) for one problem by timing trial
+// register bits, lanes, coalescing bits, VALU or MFMA stage arithmetic) for
+// one problem by timing trial
 // runs on the device, and keeps the choice in a process cache and,
 // optionally, a JSON file.  Host code only: the trials run the library's own
 // entry points on a scratch state.
@@ -121,7 +122,7 @@ spin_options to_options(const Tuned& t) {
 std::vector<Tuned> candidates(int32_t prec) {
     if (prec == SPIN_C64)
         return {{14, 5, 5, 0, 0}, {14, 5, 6, 0, 0}, {13, 5, 5, 0, 0}, {13, 4, 5, 0, 0},
-                {14, 6, 5, 0, 0}, {12, 4, 5, 0, 0}};
+                {14, 6, 5, 0, 0}, {12, 4, 5, 0, 0}, {14, 5, 5, 1, 0}};
     return {{13, 4, 4, 0, 0}, {13, 5, 4, 0, 0}, {12, 4, 4, 0, 0}, {12, 3, 4, 0, 0}};
 }
 

@@ -54,10 +54,10 @@ static int batch_resident(const spin_problem* probs, int32_t n, const std::vecto
             j.init = init ? 1 : 0;
             const int nthreads = 1 << std::max(0, pr.M - g.first.first);
             j.pro_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, g.first.first, nthreads, 1, tb, true);
+            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, tb, true);
             j.pro_nstage = int(tb.stages.size()) - j.pro_stage0;
             j.step_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.step, pr.M, pr.observed_site, g.first.first, nthreads, 1, tb, true);
+            encode_pass<T>(rp.step, pr.M, pr.observed_site, tb, true);
             j.step_nstage = int(tb.stages.size()) - j.step_stage0;
             jobs.push_back(j);
         }
@@ -177,10 +177,10 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             const int nthreads = 1 << (pr.M - R);
             b.gsize = 1;
             b.pro_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, R, nthreads, 1, tb, true);
+            encode_pass<T>(rp.prologue, pr.M, pr.observed_site, tb, true);
             b.pro_nstage = int(tb.stages.size()) - b.pro_stage0;
             b.step_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.step, pr.M, pr.observed_site, R, nthreads, 1, tb, true);
+            encode_pass<T>(rp.step, pr.M, pr.observed_site, tb, true);
             b.step_nstage = int(tb.stages.size()) - b.step_stage0;
             for (const Op& op : rp.step.ops) fops += op.kind == 0;
             // on-chip: about half the cost per amplitude of a tiled pass
@@ -192,7 +192,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             pp.c = sizeof(T) == 4 ? 5 : 4;
             StreamPlan sp = plan_stream(pr.M, Js[p], dt, n_steps, pr.observed_site, true, pp);
             b.pass0 = int(tb.passes.size());
-            for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, R, NT, V, tb);
+            for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, tb);
             b.launch0 = int64_t(launches.size());
             b.nlaunch = int(sp.launch_tmpl.size());
             for (size_t l = 0; l < sp.launch_tmpl.size(); ++l)

@@ -23,6 +23,14 @@ constexpr int kBatchRing = 16;      // observable slots per gang problem (steps 
 // phase.  kOpMeas accumulates the observable of the state at that point.
 constexpr int32_t kOpZZ = 64;
 constexpr int32_t kOpMeas = 255;
+// kOpMat (matrix engine, 32 registers per lane): multiply the lane's
+// registers by a dense 32 x 32 complex matrix, the product of consecutive
+// factors of the stage, on MFMA.  aux = index of the matrix in the matrix
+// table: kMatFloats floats per matrix, the real 64 x 64 form
+// W = [[Re U, -Im U], [Im U, Re U]] in MFMA A-operand order
+// (W[32 b + (l % 32)][2 p + l / 32] at float (32 b + p) * 64 + l).
+constexpr int32_t kOpMat = 254;
+constexpr int kMatFloats = 64 * 64;
 
 // One op of a stage.  For a factor with integrated strengths
 // (A, B) = (sum a*tau, sum b*tau) over the merged two-spin propagators:

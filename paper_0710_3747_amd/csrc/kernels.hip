@@ -322,6 +322,64 @@ __device__ __forceinline__ int run_factors(C (&v)[1 << R], const DevOp<T>* __res
     return o;
 }
 
+// ------------------------------------------------------- matrix engine
+// Dense 32 x 32 complex matrix U on the 32 registers of every lane, as the
+// real product Y = W X with X = (Re v_0..Re v_31, Im v_0..Im v_31) per lane
+// (column) and W = [[Re U, -Im U], [Im U, Re U]], on v_mfma_f32_32x32x2f32.
+// A wave holds 64 columns.  One v_permlane32_swap per pair of rows (2p,
+// 2p+1) turns the lane-per-column registers into the instruction's B
+// operands (lane l: row 2p + l/32 of column 32h + l%32, h = 0, 1); the A
+// operands are read from the matrix table (lane l: W[32b + l%32][2p + l/32]).
+// The accumulators hold Y[32b + 8(r/4) + 4(l/32) + r%4][32h + l%32] in
+// register r; one swap per register pair of h = 0, 1 returns them to the
+// lane-per-column layout.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <typename C>
+__device__ __forceinline__ float mat_row(const C (&v)[32], int m) {
+    return m < 32 ? v[m].x : v[m - 32].y;
+}
+template <typename C>
+__device__ __forceinline__ void mat_set(C (&v)[32], int m, float x) {
+    if (m < 32) v[m].x = x;
+    else v[m - 32].y = x;
+}
+
+template <typename C>
+__device__ __forceinline__ void mfma_stage(C (&v)[32], const float* __restrict__ W) {
+    const int lane = threadIdx.x & 63;
+    float bop[64];
+#pragma unroll
+    for (int p = 0; p < 32; ++p) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(mat_row(v, 2 * p)),
+                                                        __float_as_uint(mat_row(v, 2 * p + 1)),
+                                                        false, false);
+        bop[2 * p] = __uint_as_float(r[0]);
+        bop[2 * p + 1] = __uint_as_float(r[1]);
+    }
+    f32x16 d00 = {}, d01 = {}, d10 = {}, d11 = {};
+#pragma unroll
+    for (int p = 0; p < 32; ++p) {
+        const float a0 = W[p * 64 + lane], a1 = W[(32 + p) * 64 + lane];
+        d00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bop[2 * p], d00, 0, 0, 0);
+        d01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bop[2 * p + 1], d01, 0, 0, 0);
+        d10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bop[2 * p], d10, 0, 0, 0);
+        d11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bop[2 * p + 1], d11, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + r % 4;
+        const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(d00[r]), __float_as_uint(d01[r]),
+                                                         false, false);
+        mat_set(v, row, __uint_as_float(s0[0]));
+        mat_set(v, row + 4, __uint_as_float(s0[1]));
+        const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(d10[r]), __float_as_uint(d11[r]),
+                                                         false, false);
+        mat_set(v, 32 + row, __uint_as_float(s1[0]));
+        mat_set(v, 32 + row + 4, __uint_as_float(s1[1]));
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ C& lds_at(char* lds, uint32_t byte) {
     return *reinterpret_cast<C*>(lds + byte);
@@ -370,12 +428,13 @@ __device__ __forceinline__ int64_t lane_offset(const int64_t* gt, int tid) {
     return o;
 }
 
-template <typename T, int R, int NT, bool WRITES>
+template <typename T, int R, int NT, bool WRITES, int ENGINE = 0>
 __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, const DevPass& P,
                                            const DevStage* __restrict__ stages,
                                            const DevOp<T>* __restrict__ ops, unsigned wperm,
                                            unsigned G, int64_t tiles_per_member, char* ldsb,
-                                           double (&accP)[kMaxMeas], double (&accN)[kMaxMeas]) {
+                                           double (&accP)[kMaxMeas], double (&accN)[kMaxMeas],
+                                           const float* __restrict__ mats = nullptr) {
     using C = typename CT<T>::c;
     const int tid = threadIdx.x;
     const DevStage& S0 = stages[P.stage0];
@@ -414,7 +473,16 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
             const int o1 = S.op0 + S.nop;
             int o = S.op0;
             while (o < o1) {
-                o = run_factors<R>(v, ops, o, o1);
+                if constexpr (ENGINE == 1) {
+                    const DevOp<T> op = ops[o];
+                    if (op.code == kOpMat) {
+                        if constexpr (sizeof(T) == 4 && R == 5) mfma_stage(v, mats + size_t(op.aux) * kMatFloats);
+                        ++o;
+                        continue;
+                    }
+                } else {
+                    o = run_factors<R>(v, ops, o, o1);
+                }
                 if (o < o1) {    // observable of the state at this point
                     const int slot = ops[o].aux;
                     double p = 0.0, n = 0.0;
@@ -453,13 +521,14 @@ __device__ __forceinline__ void slot_sum(const double (&accP)[kMaxMeas],
 }
 
 // --------------------------------------------------------------- k_pass
-template <typename T, int R, int NT, bool WRITES>
+template <typename T, int R, int NT, bool WRITES, int ENGINE>
 __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi,
                                              const DevPass* __restrict__ passes,
                                              const DevStage* __restrict__ stages,
                                              const DevOp<T>* __restrict__ ops, int pass_index,
                                              int64_t tiles_per_wg, double* __restrict__ partials,
-                                             int64_t step_offset, int ch, int nwg) {
+                                             int64_t step_offset, int ch, int nwg,
+                                             const float* __restrict__ mats) {
     using C = typename CT<T>::c;
     constexpr int K = R + __builtin_ctz(NT);
     __shared__ C lds[1 << K];
@@ -475,8 +544,8 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
     // line.
     const unsigned G = gridDim.x, w = blockIdx.x;
     const unsigned wperm = (G >= 8) ? (w % 8u) * (G / 8u) + w / 8u : w;
-    pass_tiles<T, R, NT, WRITES>(psi, P, stages, ops, wperm, G, tiles_per_wg,
-                                 reinterpret_cast<char*>(lds), accP, accN);
+    pass_tiles<T, R, NT, WRITES, ENGINE>(psi, P, stages, ops, wperm, G, tiles_per_wg,
+                                         reinterpret_cast<char*>(lds), accP, accN, mats);
     for (int m = 0; m < P.nmeas; ++m) {
         double p, n;
         slot_sum<NT>(accP, accN, m, red, p, n);
@@ -755,19 +824,29 @@ hipError_t launch_factor(void* psi, int M, int lo, int hi, double t, double s, d
     return hipGetLastError();
 }
 
-template <typename T, int R, int NT>
+template <typename T, int R, int NT, int ENGINE = 0>
 static hipError_t pass_one(bool writes, void* psi, const DevPass* passes, const DevStage* stages,
                            const DevOp<T>* ops, int pass_index, int64_t tiles_per_wg, int nwg,
-                           double* partials, int64_t step_offset, int ch, hipStream_t st) {
+                           double* partials, int64_t step_offset, int ch, const float* mats,
+                           hipStream_t st) {
     if (writes)
-        hipLaunchKernelGGL((k_pass<T, R, NT, true>), dim3(nwg), dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_pass<T, R, NT, true, ENGINE>), dim3(nwg), dim3(NT), 0, st,
                            reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
-                           pass_index, tiles_per_wg, partials, step_offset, ch, nwg);
+                           pass_index, tiles_per_wg, partials, step_offset, ch, nwg, mats);
     else
-        hipLaunchKernelGGL((k_pass<T, R, NT, false>), dim3(nwg), dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_pass<T, R, NT, false, ENGINE>), dim3(nwg), dim3(NT), 0, st,
                            reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
-                           pass_index, tiles_per_wg, partials, step_offset, ch, nwg);
+                           pass_index, tiles_per_wg, partials, step_offset, ch, nwg, mats);
     return hipGetLastError();
+}
+
+bool pass_shape_exists(bool f32, int r, int nt, int engine) {
+    if (engine == 1) return f32 && r == 5 && nt == 512;
+    if (engine != 0) return false;
+    if (f32) return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 5 && nt == 512) ||
+                    (r == 6 && nt == 256) || (r == 4 && nt == 512) || (r == 4 && nt == 1024);
+    return (r == 4 && nt == 256) || (r == 5 && nt == 256) || (r == 4 && nt == 512) ||
+           (r == 3 && nt == 512) || (r == 3 && nt == 1024);
 }
 
 template <typename T>
@@ -775,10 +854,19 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
                        const DevStage* stages, const DevOp<T>* ops, int pass_index,
                        int64_t tiles_per_wg, int nwg, double* partials, int64_t step_offset,
                        int ch, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (sh.engine == 1) {
+            if (sh.r == 5 && sh.nt == 512 && sh.mats)
+                return pass_one<T, 5, 512, 1>(sh.writes, psi, passes, stages, ops, pass_index,
+                                              tiles_per_wg, nwg, partials, step_offset, ch, sh.mats, st);
+            return hipErrorInvalidValue;
+        }
+    }
+    if (sh.engine != 0) return hipErrorInvalidValue;
 #define SPIN_PASS(RR, NTT)                                                                   \
     if (sh.r == RR && sh.nt == NTT)                                                          \
         return pass_one<T, RR, NTT>(sh.writes, psi, passes, stages, ops, pass_index, tiles_per_wg, nwg, \
-                                    partials, step_offset, ch, st);
+                                    partials, step_offset, ch, nullptr, st);
     if constexpr (sizeof(T) == 4) {
         SPIN_PASS(5, 256) SPIN_PASS(5, 512) SPIN_PASS(4, 256) SPIN_PASS(6, 256)
         SPIN_PASS(4, 512) SPIN_PASS(4, 1024)

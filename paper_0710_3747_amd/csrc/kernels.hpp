@@ -42,7 +42,11 @@ struct PassShape {
     int r;    // register bits (amplitudes per lane = 2^r)
     int nt;   // lanes per workgroup; tile bits k = r + log2(nt)
     bool writes = true;   // false: read-only pass (observables only)
+    int engine = 0;       // 0: VALU butterflies; 1: MFMA stage matrices (complex64, r = 5, nt = 512)
+    const float* mats = nullptr;   // engine 1: device matrix table
 };
+// Whether a pass kernel is instantiated for (precision, r, nt, engine).
+bool pass_shape_exists(bool f32, int r, int nt, int engine);
 
 template <typename T>
 hipError_t launch_init(void* psi, int M, int n, uint64_t seed, hipStream_t st);

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <functional>
 #include <map>
@@ -1032,12 +1033,58 @@ uint32_t apply_layout(const std::vector<uint32_t>& img, uint32_t l) {
 
 }  // namespace
 
+namespace {
+
+// Dense product of consecutive factors on 5 register bits (32 x 32 complex,
+// FP64), applied as each factor's exact two-spin propagator: on register
+// index j with bits (qa, qb) anti-aligned, partner j' = j ^ bit qa ^ bit qb,
+//   psi_j <- e^{+iA/4} (cos(B/2) psi_j - i sin(B/2) psi_j'),
+// aligned: psi_j <- e^{-iA/4} psi_j.
+struct StageMatrix {
+    std::vector<std::complex<double>> u;   // row-major 32 x 32
+    bool any = false;
+    StageMatrix() { reset(); }
+    void reset() {
+        u.assign(32 * 32, 0.0);
+        for (int i = 0; i < 32; ++i) u[i * 32 + i] = 1.0;
+        any = false;
+    }
+    void apply(int qa, int qb, double A, double B) {
+        const double c = std::cos(0.5 * B), s = std::sin(0.5 * B);
+        const std::complex<double> pa = std::polar(1.0, 0.25 * A), pal = std::polar(1.0, -0.25 * A);
+        const std::complex<double> mis(0.0, -s);
+        std::vector<std::complex<double>> v(u);
+        for (int j = 0; j < 32; ++j) {
+            const bool anti = ((j >> qa) & 1) != ((j >> qb) & 1);
+            const int jp = j ^ (1 << qa) ^ (1 << qb);
+            for (int col = 0; col < 32; ++col)
+                v[j * 32 + col] = anti ? pa * (c * u[j * 32 + col] + mis * u[jp * 32 + col])
+                                       : pal * u[j * 32 + col];
+        }
+        u.swap(v);
+        any = true;
+    }
+    // Appends the real 64 x 64 form in MFMA A-operand order.
+    void emit(std::vector<float>& mats) const {
+        auto W = [&](int row, int col) {
+            const bool im_out = row >= 32, im_in = col >= 32;
+            const std::complex<double> z = u[(row & 31) * 32 + (col & 31)];
+            if (!im_out && !im_in) return z.real();
+            if (!im_out && im_in) return -z.imag();
+            if (im_out && !im_in) return z.imag();
+            return z.real();
+        };
+        for (int b = 0; b < 2; ++b)
+            for (int p = 0; p < 32; ++p)
+                for (int l = 0; l < 64; ++l) mats.push_back(float(W(32 * b + l % 32, 2 * p + l / 32)));
+    }
+};
+
+}  // namespace
+
 template <typename T>
-void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, int vec,
-                 DevTables<T>& out, bool fixed_swizzle) {
-    (void)r;
-    (void)nthreads;
-    (void)vec;
+void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, bool fixed_swizzle,
+                 int engine) {
     const int k = int(hp.sites.size());
     constexpr int eb = sizeof(T) * 2;
     DevPass dp{};
@@ -1127,9 +1174,21 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
                 if (hs.regs[b] == p) return b;
             throw std::runtime_error("encode: factor site not in registers");
         };
+        if (engine == 1 && rr != 5) throw std::runtime_error("encode: matrix engine needs 5 register bits");
+        StageMatrix sm;
+        auto flush = [&]() {
+            if (!sm.any) return;
+            DevOp<T> d{};
+            d.code = kOpMat;
+            d.aux = int32_t(out.mats.size() / kMatFloats);
+            sm.emit(out.mats);
+            out.ops.push_back(d);
+            sm.reset();
+        };
         for (int n : hs.ops) {
             const Op& op = hp.ops[n];
             if (op.kind == 1) {
+                flush();
                 if (nmeas >= kMaxMeas) throw std::runtime_error("encode: too many observables");
                 DevOp<T> d{};
                 d.code = kOpMeas;
@@ -1141,6 +1200,10 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
             }
             int qa = regbit(local[op.i]), qb = regbit(local[op.j]);
             if (qa > qb) std::swap(qa, qb);
+            if (engine == 1) {
+                sm.apply(qa, qb, op.A, op.B);
+                continue;
+            }
             // rotation angle theta = B/2; split until |theta| <= pi/2 so the
             // three-shear form stays well conditioned.
             double theta = 0.5 * op.B;
@@ -1160,6 +1223,7 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
                 out.ops.push_back(d);
             }
         }
+        flush();
         ds.nop = int(out.ops.size()) - ds.op0;
         out.stages.push_back(ds);
     }
@@ -1167,8 +1231,8 @@ void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, i
     out.passes.push_back(dp);
 }
 
-template void encode_pass<float>(const HostPass&, int, int, int, int, int, DevTables<float>&, bool);
-template void encode_pass<double>(const HostPass&, int, int, int, int, int, DevTables<double>&, bool);
+template void encode_pass<float>(const HostPass&, int, int, DevTables<float>&, bool, int);
+template void encode_pass<double>(const HostPass&, int, int, DevTables<double>&, bool, int);
 
 std::string describe_plan(const StreamPlan& plan) {
     std::ostringstream os;

@@ -141,14 +141,16 @@ struct DevTables {
     std::vector<DevPass> passes;
     std::vector<DevStage> stages;
     std::vector<DevOp<T>> ops;
+    std::vector<float> mats;           // matrix engine: kMatFloats per kOpMat
 };
 
 // Encodes one pass (or the stages of a one-workgroup plan) into the device
 // tables.  fixed_swizzle: use the one-workgroup kernel's fixed LDS swizzle
-// instead of a layout searched for this pass.
+// instead of a layout searched for this pass.  engine 1: the factors of each
+// stage (between observables) become one kOpMat (needs 5 register bits).
 template <typename T>
-void encode_pass(const HostPass& hp, int M, int observed, int r, int nthreads, int vec,
-                 DevTables<T>& out, bool fixed_swizzle = false);
+void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out,
+                 bool fixed_swizzle = false, int engine = 0);
 
 std::string describe_plan(const StreamPlan& plan);
 

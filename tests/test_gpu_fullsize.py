@@ -178,3 +178,16 @@ def test_maximum_sizes_single_bond(prec, M):
     k = np.arange(steps + 1)
     assert np.abs(P - 0.5 * (1 + np.cos(b * k * dt))).max() < TOL_P[prec]
     assert np.abs(N - 1).max() < (1e-10 if prec == C128 else 1e-4)
+
+
+def test_mfma_engine_ladder_2x15_sectors_and_vs_butterflies():
+    """Matrix engine at M = 30 (8 GiB complex64): sectors with <= 2 spins
+    down against the oracle, and P against the butterfly path."""
+    M, J, dt, steps = 30, workloads.ladder(15), 0.05, 20
+    note("mfma engine M=30")
+    P1, N1, _, t = gpu_evolve(C64, M, J, dt, steps, 0, seed=5, opts={"engine": 1}, keep_state=False)
+    sector_check(t, M, J, dt, steps, 5, C64, [0, 1, 2])
+    del t
+    P0, _, _, _ = gpu_evolve(C64, M, J, dt, steps, 0, seed=5, keep_state=False)
+    assert np.abs(P1 - P0).max() < 1e-5
+    assert np.abs(N1 - 1).max() < 1e-4

@@ -325,3 +325,21 @@ def test_autotune_picks_a_shape_stores_it_and_it_evolves_correctly(tmp_path):
     Pw, Nw, psiw = oracle.trotter_run(psi0, M, J, dt, steps, 0)
     assert np.abs(P - Pw).max() < TOL_P[C64]
     assert_state_close(psi, psiw, C64)
+
+
+@pytest.mark.parametrize("M,steps,a_over_b", [(18, 12, 0.0), (20, 9, -2.0), (16, 40, 0.5)])
+def test_mfma_engine_matches_oracle(M, steps, a_over_b):
+    """Matrix engine: each stage's factors fused into one 32 x 32 complex
+    matrix applied on FP32 MFMA; state and P against the oracle (FP32
+    tolerance), with and without I^z I^z terms, over several tiles."""
+    J = workloads.ladder(M // 2, a_over_b=a_over_b)
+    opts = {"engine": 1}
+    info = spq.spin_describe_plan(C64, M, J, 0.05, steps, 0, spq.Options(**opts))
+    assert info["path"] == 2 and info["engine"] == 1
+    note("mfma engine", M, steps, a_over_b)
+    P, N, psi, _ = gpu_evolve(C64, M, J, 0.05, steps, 0, seed=4, opts=opts)
+    psi0 = oracle.random_phase_state(M, 0, 4)
+    Pw, Nw, psiw = oracle.trotter_run(psi0, M, J, 0.05, steps, 0)
+    assert np.abs(P - Pw).max() < TOL_P[C64]
+    assert np.abs(N - 1).max() < 1e-4
+    assert_state_close(psi, psiw, C64)

@@ -122,3 +122,25 @@ def test_long_ladder_plan_is_periodic_and_fused():
     assert info["passes_per_step"] < 4.0          # versus 86 factors per step unfused
     info128 = spq.spin_describe_plan(spq.SPIN_C128, 30, J, 0.05, 1000, 0)
     assert info128["path"] == 2
+
+
+def test_matrix_engine_option_checks():
+    """The matrix engine exists for complex64 tiles of 2^14 with 32 registers
+    per lane; other requests are refused on the host, and the plan (and so
+    the op trace) is the butterfly plan's."""
+    J = workloads.ladder(9)
+    o = spq.Options(engine=1)
+    info = spq.spin_describe_plan(spq.SPIN_C64, 18, J, 0.05, 10, 0, o)
+    assert info["engine"] == 1 and info["reg_bits"] == 5 and info["tile_bits"] == 14
+    t1 = spq.spin_plan_trace(spq.SPIN_C64, 18, J, 0.05, 10, 0, o)
+    t0 = spq.spin_plan_trace(spq.SPIN_C64, 18, J, 0.05, 10, 0)
+    assert np.array_equal(t0, t1)
+    for prec, kw, code in [(spq.SPIN_C128, {}, spq.SPIN_EUNSUPPORTED),
+                           (spq.SPIN_C64, {"tile_bits": 13}, spq.SPIN_EUNSUPPORTED),
+                           (spq.SPIN_C64, {"reg_bits": 4}, spq.SPIN_EUNSUPPORTED)]:
+        with pytest.raises(spq.SpinError) as e:
+            spq.spin_describe_plan(prec, 18, J, 0.05, 10, 0, spq.Options(engine=1, **kw))
+        assert e.value.code == code
+    with pytest.raises(spq.SpinError) as e:
+        spq.spin_describe_plan(spq.SPIN_C64, 18, J, 0.05, 10, 0, spq.Options(engine=2))
+    assert e.value.code == spq.SPIN_EINVAL
