@@ -416,16 +416,16 @@ std::vector<Op> gen_sequence(int M, const std::vector<Coupling>& J, double dt, i
 }  // namespace
 
 // ----------------------------------------------------------------- stages
-void plan_stages_coalesced(HostPass& pass, int r, int c) {
+void plan_stages_coalesced(HostPass& pass, int r, int c, int beam) {
     uint32_t af = 0, al = 0;
     for (size_t p = 0; p < pass.sites.size(); ++p) {
         if (pass.bit_in[p] < c) af |= 1u << p;
         if (pass.bit_out[p] < c) al |= 1u << p;
     }
-    plan_stages(pass, r, af, al);
+    plan_stages(pass, r, af, al, beam);
 }
 
-void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_last) {
+void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_last, int beam) {
     const int k = int(pass.sites.size());
     const int nops = int(pass.ops.size());
     std::vector<int> local(kMaxSites, -1);
@@ -453,25 +453,32 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_las
             pj[n] = pi[n];
         }
     }
-    std::vector<int> head(k + 1, 0);
-    std::vector<char> done(nops, 0);
-    int ndone = 0;
     auto ready = [&](int n, const std::vector<int>& h) {
         return h[li[n]] == pi[n] && h[lj[n]] == pj[n];
     };
-    while (ndone < nops) {
-        // Greedy growth from the earliest ready ops; try a few seeds.
-        int best_cnt = -1;
-        std::vector<int> best_ops;
-        uint32_t best_S = 0;
+    struct State {
+        std::vector<int> head;
+        std::vector<char> done;
+        int ndone = 0;
+        std::vector<HostStage> stages;
+    };
+    struct Cand {
+        uint32_t S;
+        std::vector<int> ops;
+        int cnt;
+    };
+    // Register sets for the next stage: greedy growth from a few ready ops,
+    // best first.  The first stage's registers may not take the avoided
+    // positions.
+    auto candidates = [&](const State& st, int nseeds) {
         std::vector<int> seeds;
-        for (int n = 0; n < nops && int(seeds.size()) < 6; ++n)
-            if (!done[n] && ready(n, head) && pass.ops[n].kind == 0) seeds.push_back(n);
+        for (int n = 0; n < nops && int(seeds.size()) < nseeds; ++n)
+            if (!st.done[n] && ready(n, st.head) && pass.ops[n].kind == 0) seeds.push_back(n);
         if (seeds.empty()) seeds.push_back(-1);
-        // the first stage's registers may not take the avoided positions
-        const uint32_t avoid = pass.stages.empty() ? avoid_first : 0u;
+        const uint32_t avoid = st.stages.empty() ? avoid_first : 0u;
+        std::vector<Cand> out;
         for (int seed : seeds) {
-            std::vector<int> h = head;
+            std::vector<int> h = st.head;
             uint32_t S = 0;
             if (seed >= 0) S = (1u << li[seed]) | (1u << lj[seed]);
             if (S & avoid) S = 0;
@@ -482,7 +489,7 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_las
             while (changed) {
                 changed = false;
                 for (int n = 0; n < nops; ++n) {
-                    if (done[n] || taken[n] || !ready(n, h)) continue;
+                    if (st.done[n] || taken[n] || !ready(n, h)) continue;
                     const Op& op = pass.ops[n];
                     if (op.kind == 0) {
                         uint32_t need = (1u << li[n]) | (1u << lj[n]);
@@ -498,36 +505,89 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_las
                     changed = true;
                 }
             }
-            if (cnt > best_cnt) {
-                best_cnt = cnt;
-                best_ops = got;
-                best_S = S;
-            }
+            bool dup = false;
+            for (const Cand& c : out) dup |= c.S == S && c.cnt == cnt;
+            if (!dup) out.push_back(Cand{S, got, cnt});
         }
-        if (best_ops.empty() && !pass.stages.empty())
-            throw std::runtime_error("planner: stage made no progress");
+        std::stable_sort(out.begin(), out.end(), [](const Cand& a, const Cand& b) { return a.cnt > b.cnt; });
+        return out;
+    };
+    auto advance = [&](const State& st, const Cand& c) {
+        State nx = st;
+        uint32_t S = c.S;
+        const uint32_t avoid = st.stages.empty() ? avoid_first : 0u;
         // Fill the register set up to r positions, highest positions first
         // (keeps the lanes on low positions), never the avoided ones and
         // preferably not the last stage's.
         for (int pass2 = 0; pass2 < 2; ++pass2)
-            for (int p = k - 1; p >= 0 && __builtin_popcount(best_S) < std::min(r, k); --p) {
+            for (int p = k - 1; p >= 0 && __builtin_popcount(S) < std::min(r, k); --p) {
                 if ((avoid >> p) & 1u) continue;
                 if (pass2 == 0 && ((avoid_last >> p) & 1u)) continue;
-                best_S |= 1u << p;
+                S |= 1u << p;
             }
-        HostStage st;
+        HostStage hs;
         for (int p = 0; p < k; ++p)
-            if (best_S & (1u << p)) st.regs.push_back(p);
-        std::sort(best_ops.begin(), best_ops.end());
-        for (int n : best_ops) {
-            done[n] = 1;
-            ++ndone;
-            head[li[n]] = std::max(head[li[n]], pi[n] + 1);
-            head[lj[n]] = std::max(head[lj[n]], pj[n] + 1);
+            if (S & (1u << p)) hs.regs.push_back(p);
+        std::vector<int> ops = c.ops;
+        std::sort(ops.begin(), ops.end());
+        for (int n : ops) {
+            nx.done[n] = 1;
+            ++nx.ndone;
+            nx.head[li[n]] = std::max(nx.head[li[n]], pi[n] + 1);
+            nx.head[lj[n]] = std::max(nx.head[lj[n]], pj[n] + 1);
         }
-        st.ops = best_ops;
-        pass.stages.push_back(std::move(st));
+        hs.ops = ops;
+        nx.stages.push_back(std::move(hs));
+        return nx;
+    };
+    // A finished stage list still needs an extra stage when its last stage
+    // holds an output low-bit position (or is a lone stage that moves data).
+    auto penalty = [&](const State& st) {
+        uint32_t m = 0;
+        for (int p : st.stages.back().regs) m |= 1u << p;
+        if (st.stages.size() == 1) return (m & (avoid_first | avoid_last)) != 0 || pass.bit_in != pass.bit_out;
+        return (m & avoid_last) != 0;
+    };
+    // Beam search over stage sequences (width 1: the greedy choice); a
+    // level adds one stage to every kept sequence.
+    State init;
+    init.head.assign(k + 1, 0);
+    init.done.assign(nops, 0);
+    std::vector<State> level{init};
+    State best;
+    bool have = false;
+    const int width = std::max(1, beam);
+    const int nseeds = width > 1 ? 12 : 6;
+    const int per_state = width > 1 ? 3 : 1;
+    while (!have) {
+        if (level.front().ndone == nops) {   // no ops at all
+            best = level.front();
+            break;
+        }
+        std::vector<State> next;
+        for (const State& st : level) {
+            auto cs = candidates(st, nseeds);
+            if (cs.front().ops.empty() && !st.stages.empty())
+                throw std::runtime_error("planner: stage made no progress");
+            for (int i = 0; i < int(cs.size()) && i < per_state; ++i) next.push_back(advance(st, cs[i]));
+        }
+        std::stable_sort(next.begin(), next.end(),
+                         [](const State& a, const State& b) { return a.ndone > b.ndone; });
+        std::vector<State> kept;
+        for (State& st : next) {
+            bool dup = false;
+            for (const State& o : kept) dup |= o.done == st.done;
+            if (!dup) kept.push_back(std::move(st));
+            if (int(kept.size()) == width) break;
+        }
+        for (const State& st : kept)
+            if (st.ndone == nops && (!have || (penalty(best) && !penalty(st)))) {
+                best = st;
+                have = true;
+            }
+        level = std::move(kept);
     }
+    pass.stages = std::move(best.stages);
     // a pass always has a stage; the last one must be storable directly
     // A single stage stores from the registers it loaded with no workgroup
     // barrier in between, so each lane must store exactly the addresses it
@@ -881,6 +941,14 @@ StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, in
             best_cost = c;
         }
     }
+    // The chosen plan's register stages again, with a beam search (too slow
+    // for every variant); a pass keeps whichever staging is shorter.
+    if (nv > 1)
+        for (HostPass& hp : best.passes) {
+            HostPass alt = hp;
+            plan_stages_coalesced(alt, std::min(pp.r, int(alt.sites.size())), pp.c, 32);
+            if (alt.stages.size() < hp.stages.size()) hp.stages = std::move(alt.stages);
+        }
     return best;
 }
 

@@ -105,10 +105,12 @@ struct StreamPlan {
 // the last stored straight back, so their register sets must avoid the
 // positions holding the coalescing address bits (avoid_first / avoid_last,
 // masks of tile-local positions); empty stages are added where needed.
-void plan_stages(HostPass& pass, int r, uint32_t avoid_first = 0, uint32_t avoid_last = 0);
+// beam: width of the search over stage sequences (1 = greedy).
+void plan_stages(HostPass& pass, int r, uint32_t avoid_first = 0, uint32_t avoid_last = 0,
+                 int beam = 1);
 // Same, with the masks taken from the pass's layouts: positions whose input
 // (output) global bit is below c.
-void plan_stages_coalesced(HostPass& pass, int r, int c);
+void plan_stages_coalesced(HostPass& pass, int r, int c, int beam = 1);
 
 // Full streaming plan for one scheduling variant: sequence, passes, period
 // search, stages.
