@@ -132,6 +132,50 @@ def run_batch(spq, torch, reps=2):
             "amplitude_updates": upd, "state_bytes": sum(8 * 2 ** p["M"] for p in spec)}
 
 
+def run_ensemble(spq, torch, L=7, steps=100, dt=0.05, draws=256):
+    """The method's own speed-up: the 2^(M-1) basis-state members of the
+    ensemble (Eq. (1)) evolved in one batched launch, against one
+    random-phase state (Eq. (2)) and a batch of independent phase draws."""
+    import numpy as np
+    import workloads
+    M = 2 * L
+    J = workloads.ladder(L)
+    xs = [x for x in range(2 ** M) if not (x & 1)]
+
+    def batch(seeds, init):
+        big = torch.empty(len(seeds), 2 ** M, dtype=torch.complex64, device="cuda")
+        Pb = torch.zeros(len(seeds), steps + 1, dtype=torch.float64, device="cuda")
+        probs = [dict(psi=big[i], M=M, couplings=J, observed_site=0, polarized_site=0, seed=int(x),
+                      P=Pb[i]) for i, x in enumerate(seeds)]
+        spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)   # plans, warms
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, Pb.cpu().numpy()
+
+    t_ens, P_ens = batch(xs, spq.SPIN_INIT_BASIS)
+    t_draws, P_draws = batch(list(range(draws)), spq.SPIN_INIT_RANDOM_PHASE)
+    psi = torch.empty(2 ** M, dtype=torch.complex64, device="cuda")
+    P1 = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+    for rep in range(2):
+        spq.spin_init_random_phase(psi, M, 0, 7)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        spq.spin_trotter_evolve(psi, M, J, dt, steps, 0, P1)
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+    Pbar = P_ens.mean(0)
+    return {"workload": f"ladder_2x{L}_xy", "M": M, "steps": steps, "dt": dt,
+            "ensemble_members": len(xs), "ensemble_seconds": t_ens,
+            "one_random_phase_seconds": t_one,
+            "ensemble_over_one_state": t_ens / t_one,
+            "phase_draws": draws, "phase_draws_seconds": t_draws,
+            "max_dP_one_state_vs_ensemble": float(np.abs(P1.cpu().numpy() - Pbar).max()),
+            "max_dP_mean_of_draws_vs_ensemble": float(np.abs(P_draws.mean(0) - Pbar).max()),
+            "bound_std_one_state": 2.0 * 2.0 ** (-(M - 1) / 2)}
+
+
 def measured_traffic(prec_key):
     """HBM bytes per pass-kernel launch from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
@@ -203,7 +247,8 @@ def main():
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--coalesce-bits", type=int, default=0)
     ap.add_argument("--workload", default="ladder_2x15",
-                    choices=["ladder_2x15", "ladder_2x12", "ladder_2x5", "star_28", "batch_stars"])
+                    choices=["ladder_2x15", "ladder_2x12", "ladder_2x5", "star_28", "batch_stars",
+                             "ensemble"])
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-stars extra")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default launch shape instead of the autotuner's choice")
@@ -225,6 +270,9 @@ def main():
         copy_probe(torch)
         return
     spq.load_library()
+    if args.workload == "ensemble":
+        print(json.dumps(run_ensemble(spq, torch)), flush=True)
+        return
     if args.workload == "batch_stars":
         print(json.dumps(run_batch(spq, torch)), flush=True)
         return
@@ -331,6 +379,8 @@ def main():
     elif not args.no_batch:
         print("[bench] batched stars", file=sys.stderr, flush=True)
         out["batch_stars"] = run_batch(spq, torch)
+        print("[bench] basis-state ensemble vs random phase", file=sys.stderr, flush=True)
+        out["ensemble_vs_random_phase"] = run_ensemble(spq, torch)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(w)

@@ -144,33 +144,42 @@ int spin_local_polarization(const void *psi, int32_t prec, int32_t M, int32_t si
 
 /*
  * Batched evolution of independent problems of uneven size (disorder
- * realisations, or independent phase draws whose mean is Eq. (4)), in ONE
+ * realisations, independent phase draws whose mean is Eq. (4), or the
+ * 2^(M-1) basis-state members of the ensemble average of Eq. (1)), in ONE
  * persistent launch.  Every problem uses the same prec, dt and n_steps.
  */
 typedef struct {
     void *psi;               /* device state of this problem, 2^M amplitudes */
     int32_t M, K;            /* size and number of couplings */
     int64_t coupling_offset; /* index of its first coupling in J_all */
-    int32_t polarized_site;  /* used when init_random_phase != 0 */
+    int32_t polarized_site;  /* used with SPIN_INIT_RANDOM_PHASE */
     int32_t observed_site;
-    uint64_t seed;           /* phase seed when init_random_phase != 0 */
+    uint64_t seed;           /* phase seed (SPIN_INIT_RANDOM_PHASE) or basis index (SPIN_INIT_BASIS) */
     double *P_dev;           /* n_steps+1 FP64 entries (required) */
     double *N_dev;           /* n_steps+1 FP64 entries or NULL */
 } spin_problem;
 
+/* Initial state written inside the batched launch. */
+enum {
+    SPIN_INIT_NONE = 0,          /* evolve the states as given */
+    SPIN_INIT_RANDOM_PHASE = 1,  /* as spin_init_random_phase(polarized_site, seed) */
+    SPIN_INIT_BASIS = 2          /* the basis state |seed> (0 <= seed < 2^M): one member
+                                    |Psi_i> of the ensemble of Eq. (1) */
+};
+
 /*
  * spin_trotter_evolve_batch -- for every problem, optionally write its
- * random-phase state (as spin_init_random_phase), then evolve it n_steps
- * steps (as spin_trotter_evolve) writing its P and N.
+ * initial state (`init`, one of SPIN_INIT_*), then evolve it n_steps steps
+ * (as spin_trotter_evolve) writing its P and N.
  *   probs, n       : host array of n >= 0 problems (read during the call).
  *   J_all, K_total : host array holding every problem's couplings.
- *   init_random_phase : 1 = initialise each state inside the launch first.
- * The states must not overlap.  Errors as spin_trotter_evolve, reported for
- * the first offending problem.
+ * The states must not overlap.  The call synchronises `stream`.  Errors as
+ * spin_trotter_evolve (plus SPIN_EINVAL for a bad init or a basis index
+ * >= 2^M), reported for the first offending problem.
  */
 int spin_trotter_evolve_batch(const spin_problem *probs, int32_t n, const spin_coupling *J_all,
                               int64_t K_total, int32_t prec, double dt, int64_t n_steps,
-                              int32_t init_random_phase, void *stream);
+                              int32_t init, void *stream);
 
 /*
  * spin_prepare_plan -- plans the call spin_trotter_evolve_ex would make with

@@ -26,6 +26,7 @@ __all__ = [
 
 SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EHIP, SPIN_EUNSUPPORTED, SPIN_ENOTFOUND = 0, -1, -2, -3, -4, -5
 SPIN_C64, SPIN_C128 = 1, 2
+SPIN_INIT_NONE, SPIN_INIT_RANDOM_PHASE, SPIN_INIT_BASIS = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "libspinqp.so")
@@ -210,12 +211,17 @@ def spin_local_polarization(psi, M: int, site: int, out, stream=None) -> None:
 
 
 def spin_trotter_evolve_batch(problems: Sequence[dict], prec: int, dt: float, n_steps: int,
-                              init_random_phase: bool = True, stream=None) -> None:
+                              init_random_phase: bool = True, stream=None,
+                              init: Optional[int] = None) -> None:
     """Evolves independent problems in one launch.
 
     Each problem is a dict with keys psi (device tensor), M, couplings,
-    observed_site, P, optional N, polarized_site and seed.
+    observed_site, P, optional N, polarized_site and seed.  `init` (one of
+    SPIN_INIT_*) overrides init_random_phase; with SPIN_INIT_BASIS the seed
+    is the basis index of the problem's initial state.
     """
+    if init is None:
+        init = SPIN_INIT_RANDOM_PHASE if init_random_phase else SPIN_INIT_NONE
     lib = load_library()
     allJ = []
     arr = (Problem * max(1, len(problems)))()
@@ -237,8 +243,7 @@ def spin_trotter_evolve_batch(problems: Sequence[dict], prec: int, dt: float, n_
         arr[n].N_dev = Nt.value if Nt is not None else None
     carr, Ktot = _couplings(allJ)
     _check(lib.spin_trotter_evolve_batch(arr, len(problems), carr, Ktot, prec, float(dt),
-                                         int(n_steps), 1 if init_random_phase else 0,
-                                         _stream(stream)))
+                                         int(n_steps), int(init), _stream(stream)))
 
 
 def spin_prepare_plan(prec: int, M: int, couplings, dt: float, n_steps: int, observed_site: int,

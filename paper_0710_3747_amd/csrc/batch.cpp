@@ -36,29 +36,43 @@ static int batch_resident(const spin_problem* probs, int32_t n, const std::vecto
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return probs[a].M > probs[b].M; });
         DevTables<T> tb;
         std::vector<ResidentJob> jobs;
+        std::map<std::vector<double>, ResidentJob> shared;   // equal problems share tables
         for (int p : idx) {
             const spin_problem& pr = probs[p];
-            ResidentPlan rp;
-            try {
-                rp = plan_resident(pr.M, Js[p], dt, pr.observed_site, true, g.first.first);
-            } catch (const std::exception& e) {
-                return fail(SPIN_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+            std::vector<double> skey{double(pr.M), double(pr.observed_site)};
+            for (const Coupling& c : Js[p]) {
+                skey.push_back(c.i);
+                skey.push_back(c.j);
+                skey.push_back(c.a);
+                skey.push_back(c.b);
             }
             ResidentJob j{};
+            auto hit = shared.find(skey);
+            if (hit != shared.end()) j = hit->second;
             j.psi = pr.psi;
             j.P = pr.P_dev;
             j.N = pr.N_dev;
             j.seed = pr.seed;
             j.M = pr.M;
             j.polarized = pr.polarized_site;
-            j.init = init ? 1 : 0;
-            const int nthreads = 1 << std::max(0, pr.M - g.first.first);
+            j.init = init;
+            if (hit != shared.end()) {
+                jobs.push_back(j);
+                continue;
+            }
+            ResidentPlan rp;
+            try {
+                rp = plan_resident(pr.M, Js[p], dt, pr.observed_site, true, g.first.first);
+            } catch (const std::exception& e) {
+                return fail(SPIN_EUNSUPPORTED, std::string("planning failed: ") + e.what());
+            }
             j.pro_stage0 = int(tb.stages.size());
             encode_pass<T>(rp.prologue, pr.M, pr.observed_site, tb, true);
             j.pro_nstage = int(tb.stages.size()) - j.pro_stage0;
             j.step_stage0 = int(tb.stages.size());
             encode_pass<T>(rp.step, pr.M, pr.observed_site, tb, true);
             j.step_nstage = int(tb.stages.size()) - j.step_stage0;
+            shared[skey] = j;
             jobs.push_back(j);
         }
         // tables live until the launch has run: allocate, copy, launch, free
@@ -161,17 +175,42 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
     std::vector<double> dur;
     int64_t part = 0;
     int ncounter = 0;
+    // problems with equal (M, observed site, couplings) share their tables
+    // (e.g. the basis-state members of one ensemble)
+    std::map<std::vector<double>, std::pair<BatchProblem, double>> shared;
     for (int p : sel) {
         const spin_problem& pr = probs[p];
+        std::vector<double> skey{double(pr.M), double(pr.observed_site)};
+        for (const Coupling& c : Js[p]) {
+            skey.push_back(c.i);
+            skey.push_back(c.j);
+            skey.push_back(c.a);
+            skey.push_back(c.b);
+        }
         BatchProblem b{};
+        double fops = 0;
+        auto hit = shared.find(skey);
+        if (hit != shared.end()) {
+            b = hit->second.first;
+            fops = hit->second.second;
+            if (b.gsize > 1 || b.M > K) {   // gang: own partial sums and counter
+                b.part0 = part;
+                part += int64_t(kBatchRing) * b.gsize * 2;
+                b.counter = ncounter++;
+            }
+        }
         b.psi = pr.psi;
         b.P = pr.P_dev;
         b.N = pr.N_dev;
         b.seed = pr.seed;
         b.M = pr.M;
         b.polarized = pr.polarized_site;
-        b.init = init ? 1 : 0;
-        double fops = 0;
+        b.init = init;
+        if (hit != shared.end()) {
+            dur.push_back(fops);
+            bp.push_back(b);
+            continue;
+        }
         if (pr.M <= K) {
             ResidentPlan rp = plan_resident(pr.M, Js[p], dt, pr.observed_site, true, R);
             const int nthreads = 1 << (pr.M - R);
@@ -184,7 +223,8 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             b.step_nstage = int(tb.stages.size()) - b.step_stage0;
             for (const Op& op : rp.step.ops) fops += op.kind == 0;
             // on-chip: about half the cost per amplitude of a tiled pass
-            dur.push_back(0.5 * fops * std::ldexp(1.0, pr.M) * double(n_steps + 1));
+            fops = 0.5 * fops * std::ldexp(1.0, pr.M) * double(n_steps + 1);
+            dur.push_back(fops);
         } else {
             PassParams pp;
             pp.k = K;
@@ -205,8 +245,10 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             for (int t : sp.launch_tmpl)
                 for (const Op& op : sp.passes[t].ops) fops += op.kind == 0;
             // factor work plus one sweep per launch, shared by the gang
-            dur.push_back((fops + 6.0 * sp.launch_tmpl.size()) * std::ldexp(1.0, pr.M) / b.gsize);
+            fops = (fops + 6.0 * sp.launch_tmpl.size()) * std::ldexp(1.0, pr.M) / b.gsize;
+            dur.push_back(fops);
         }
+        shared[skey] = {b, fops};
         bp.push_back(b);
     }
     // Gang schedule: slots w with the same w % 8 form an XCD group; longest
@@ -364,8 +406,9 @@ using namespace spinqp;
 extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
                                          const spin_coupling* J_all, int64_t K_total,
                                          int32_t prec, double dt, int64_t n_steps,
-                                         int32_t init_random_phase, void* stream) {
+                                         int32_t init, void* stream) {
     try {
+        if (init < SPIN_INIT_NONE || init > SPIN_INIT_BASIS) return fail(SPIN_EINVAL, "bad init");
         if (n < 0) return fail(SPIN_EINVAL, "n < 0");
         if (n > 0 && !probs) return fail(SPIN_EINVAL, "probs is NULL");
         if (K_total < 0 || (K_total > 0 && !J_all)) return fail(SPIN_EINVAL, "bad J_all / K_total");
@@ -383,8 +426,10 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
             if (!pr.P_dev) return fail(SPIN_EINVAL, os.str() + "P_dev is NULL");
             if (pr.observed_site < 0 || pr.observed_site >= pr.M)
                 return fail(SPIN_EINVAL, os.str() + "observed_site out of range");
-            if (init_random_phase && (pr.polarized_site < 0 || pr.polarized_site >= pr.M))
+            if (init == SPIN_INIT_RANDOM_PHASE && (pr.polarized_site < 0 || pr.polarized_site >= pr.M))
                 return fail(SPIN_EINVAL, os.str() + "polarized_site out of range");
+            if (init == SPIN_INIT_BASIS && (pr.seed >> pr.M) != 0)
+                return fail(SPIN_EINVAL, os.str() + "basis index (seed) >= 2^M");
             if (pr.K < 0 || pr.coupling_offset < 0 || pr.coupling_offset + pr.K > K_total)
                 return fail(SPIN_EINVAL, os.str() + "coupling range outside J_all");
             rc = validate_couplings(pr.M, J_all + pr.coupling_offset, pr.K, &Js[p]);
@@ -406,14 +451,14 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
                 sp.push_back(probs[p]);
                 sj.push_back(Js[p]);
             }
-            rc = prec == SPIN_C64 ? batch_resident<float>(sp.data(), int(sp.size()), sj, dt, n_steps, init_random_phase, st)
-                                  : batch_resident<double>(sp.data(), int(sp.size()), sj, dt, n_steps, init_random_phase, st);
+            rc = prec == SPIN_C64 ? batch_resident<float>(sp.data(), int(sp.size()), sj, dt, n_steps, init, st)
+                                  : batch_resident<double>(sp.data(), int(sp.size()), sj, dt, n_steps, init, st);
             if (rc) return rc;
         }
         if (!big.empty()) {
             const bool graph = true;
-            rc = prec == SPIN_C64 ? batch_persistent<float>(probs, big, Js, prec, dt, n_steps, init_random_phase, graph, st)
-                                  : batch_persistent<double>(probs, big, Js, prec, dt, n_steps, init_random_phase, graph, st);
+            rc = prec == SPIN_C64 ? batch_persistent<float>(probs, big, Js, prec, dt, n_steps, init, graph, st)
+                                  : batch_persistent<double>(probs, big, Js, prec, dt, n_steps, init, graph, st);
         }
         if (rc == SPIN_OK) fail(SPIN_OK, "");
         return rc;

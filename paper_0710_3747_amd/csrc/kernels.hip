@@ -53,6 +53,18 @@ __device__ __forceinline__ void random_phase_amp(uint64_t x, int n, uint64_t see
     *im = s * scale;
 }
 
+// Initial amplitude of basis state x: init 1 = the random-phase state,
+// init 2 = the basis state |seed> (one ensemble member of Eq. (1)).
+__device__ __forceinline__ void init_amp(uint64_t x, int init, int polarized, uint64_t seed,
+                                         double scale, double* re, double* im) {
+    if (init == 2) {
+        *re = x == seed ? 1.0 : 0.0;
+        *im = 0.0;
+    } else {
+        random_phase_amp(x, polarized, seed, scale, re, im);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_init(typename CT<T>::c* __restrict__ psi, int M, int n,
                                               uint64_t seed, double scale) {
@@ -578,7 +590,7 @@ __device__ __forceinline__ void resident_run(const ResidentJob& J, const DevStag
         const double scale = 1.0 / sqrt(ldexp(1.0, M - 1));
         for (uint32_t x = tid; x < dim; x += NT) {
             double re, im;
-            random_phase_amp(x, J.polarized, J.seed, scale, &re, &im);
+            init_amp(x, J.init, J.polarized, J.seed, scale, &re, &im);
             C c;
             c.x = T(re);
             c.y = T(im);
@@ -726,7 +738,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BatchProblem* __restrict__ p
             const double scale = 1.0 / sqrt(ldexp(1.0, B.M - 1));
             for (uint64_t x = uint64_t(rank) * NT + tid; x < dim; x += uint64_t(G) * NT) {
                 double re, im;
-                random_phase_amp(x, B.polarized, B.seed, scale, &re, &im);
+                init_amp(x, B.init, B.polarized, B.seed, scale, &re, &im);
                 C c;
                 c.x = T(re);
                 c.y = T(im);

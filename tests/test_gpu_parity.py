@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads
-from oracle import cref
+from oracle import cref, ed
 import paper_0710_3747_amd as spq
 from gpu_helpers import TOL_P, assert_state_close, gpu_evolve, gpu_state, note
 
@@ -284,11 +284,14 @@ def test_batch_config_256_uneven_stars():
         P, N = p["P"].cpu().numpy(), p["N"].cpu().numpy()
         assert np.isfinite(P).all() and abs(P[0] - 1) < 1e-6
         assert np.abs(N - 1).max() < 1e-4
+    # the single path searches scheduling variants for calls this long, the
+    # batch takes the default one: the same product, grouped differently,
+    # so the two agree to FP32 rounding
     picks = [int(np.argmin([p["M"] for p in probs])), 7, int(np.argmax([p["M"] for p in probs]))]
     for i in picks:
         p = probs[i]
         P, _, _, _ = gpu_evolve(C64, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"], keep_state=False)
-        assert np.abs(p["P"].cpu().numpy() - P).max() < 1e-12
+        assert np.abs(p["P"].cpu().numpy() - P).max() < 2e-5
     p = probs[picks[0]]     # the oracle on a smallest problem, full run
     Pw, _, _ = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
     assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[C64]
@@ -343,3 +346,52 @@ def test_mfma_engine_matches_oracle(M, steps, a_over_b):
     assert np.abs(P - Pw).max() < TOL_P[C64]
     assert np.abs(N - 1).max() < 1e-4
     assert_state_close(psi, psiw, C64)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ensemble_of_basis_states_matches_trotterised_ensemble(prec):
+    """The literal ensemble of Eq. (1) on the GPU: all 2^9 basis states of the
+    2 x 5 ladder with site 0 up, each evolved 400 steps in one batched launch
+    (SPIN_INIT_BASIS), averaged; against the oracle's Trotterised ensemble
+    (sector step matrices, FP64)."""
+    import torch
+    M, (L, dt, steps, seed) = 10, workloads.LADDER_CONFIGS["ladder_2x5"]
+    J = workloads.ladder(L)
+    xs = [x for x in range(2 ** M) if not (x & 1)]
+    dtype = torch.complex64 if prec == C64 else torch.complex128
+    note("basis ensemble 2x5", prec)
+    probs = [dict(psi=torch.empty(2 ** M, dtype=dtype, device="cuda"), M=M, couplings=J,
+                  observed_site=0, seed=x, P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"))
+             for x in xs]
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init=spq.SPIN_INIT_BASIS)
+    torch.cuda.synchronize()
+    Pbar = torch.stack([p["P"] for p in probs]).mean(0).cpu().numpy()
+    want = ed.ensemble_P_trotter(M, J, dt, steps, 0, 0)
+    assert np.abs(Pbar - want).max() < (1e-10 if prec == C128 else 1e-4)
+    # one member against the oracle loop, element by element
+    x = xs[37]
+    psi0 = np.zeros(2 ** M, dtype=np.complex128)
+    psi0[x] = 1.0
+    Pw, _, psiw = oracle.trotter_run(psi0, M, J, dt, steps, 0)
+    assert np.abs(probs[37]["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
+    assert_state_close(probs[37]["psi"].cpu().numpy().astype(np.complex128), psiw, prec)
+
+
+def test_basis_init_on_the_gang_path():
+    """SPIN_INIT_BASIS for states larger than one workgroup (M = 16, gangs of
+    workgroups over shared pass tables)."""
+    import torch
+    M, J, dt, steps = 16, workloads.ladder(8), 0.05, 10
+    xs = [0b0000000000000010, 0b0101001000011100, 2 ** 16 - 2]
+    note("basis init gangs")
+    probs = [dict(psi=torch.empty(2 ** M, dtype=torch.complex128, device="cuda"), M=M, couplings=J,
+                  observed_site=3, seed=x, P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"))
+             for x in xs]
+    spq.spin_trotter_evolve_batch(probs, C128, dt, steps, init=spq.SPIN_INIT_BASIS)
+    torch.cuda.synchronize()
+    for pr, x in zip(probs, xs):
+        psi0 = np.zeros(2 ** M, dtype=np.complex128)
+        psi0[x] = 1.0
+        Pw, _, psiw = oracle.trotter_run(psi0, M, J, dt, steps, 3)
+        assert np.abs(pr["P"].cpu().numpy() - Pw).max() < TOL_P[C128]
+        assert_state_close(pr["psi"].cpu().numpy(), psiw, C128)

@@ -144,3 +144,21 @@ def test_matrix_engine_option_checks():
     with pytest.raises(spq.SpinError) as e:
         spq.spin_describe_plan(spq.SPIN_C64, 18, J, 0.05, 10, 0, spq.Options(engine=2))
     assert e.value.code == spq.SPIN_EINVAL
+
+
+def test_batch_rejects_bad_init_and_basis_index():
+    """Argument errors of the batched call are found on the host before any
+    device work (the state pointer is never dereferenced)."""
+    lib = spq.load_library()
+    arr, K = spq._couplings([(0, 1, 0.0, 1.0)])
+    pr = (spq.Problem * 1)()
+    pr[0].psi = 16
+    pr[0].M = 4
+    pr[0].K = 1
+    pr[0].observed_site = 0
+    pr[0].P_dev = 16
+    pr[0].seed = 16          # basis index 16 >= 2^4
+    rc = lib.spin_trotter_evolve_batch(pr, 1, arr, K, spq.SPIN_C64, 0.1, 3, spq.SPIN_INIT_BASIS, None)
+    assert rc == spq.SPIN_EINVAL and "basis index" in spq.spin_last_error()
+    rc = lib.spin_trotter_evolve_batch(pr, 1, arr, K, spq.SPIN_C64, 0.1, 3, 7, None)
+    assert rc == spq.SPIN_EINVAL and "init" in spq.spin_last_error()
