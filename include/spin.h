@@ -134,6 +134,32 @@ int spin_trotter_evolve_ex(void *psi, int32_t prec, int32_t M, const spin_coupli
                            void *stream);
 
 /*
+ * observed_site value that selects the all-site profile's plan in
+ * spin_prepare_plan, spin_describe_plan and spin_plan_trace.
+ */
+#define SPIN_ALL_SITES (-1)
+
+/*
+ * spin_trotter_evolve_profile -- as spin_trotter_evolve_ex, but the local
+ * polarisation of Eq. (2) is read at EVERY site n' = 0..M-1 after every step
+ * (the polarisation profile of the chain, not one site), in the same launches
+ * that apply the propagators.
+ *   Pall_dev : device FP64 array of (n_steps+1) * M entries, row-major:
+ *              Pall_dev[k*M + n'] = sum_x (1 - 2 bit_n'(x)) |psi_x|^2 after k
+ *              steps.  Required.
+ *   N_dev    : device FP64 array of n_steps+1 entries for the norm, or NULL.
+ *   opt      : as spin_trotter_evolve_ex; the matrix engine (engine = 1) is
+ *              refused with SPIN_EUNSUPPORTED.
+ * The factor order, merging and final state are those of spin_trotter_evolve_ex;
+ * the tiled plan differs only in where the M observables of each step are
+ * taken (spin_plan_trace with observed_site = SPIN_ALL_SITES lists them).
+ * Errors as spin_trotter_evolve_ex.
+ */
+int spin_trotter_evolve_profile(void *psi, int32_t prec, int32_t M, const spin_coupling *J,
+                                int32_t K, double dt, int64_t n_steps, double *Pall_dev,
+                                double *N_dev, const spin_options *opt, void *stream);
+
+/*
  * spin_local_polarization -- P = sum_x (1 - 2 bit_site(x)) |psi_x|^2 and the
  * norm, FP64, of the state as it is (Eq. (2), P = 2(W - 1/2)).
  *   out_dev : device FP64 array of 2 entries: out_dev[0] = P, out_dev[1] = N.
@@ -187,7 +213,8 @@ int spin_trotter_evolve_batch(const spin_problem *probs, int32_t n, const spin_c
  * uploads the plan tables to the current device, where they stay cached
  * until spin_release_caches.  A later evolve call with equal arguments then
  * does no host planning and no table upload.  No state is touched; the
- * upload is synchronous.  Errors as spin_trotter_evolve_ex (argument
+ * upload is synchronous.  observed_site = SPIN_ALL_SITES prepares the plan
+ * of spin_trotter_evolve_profile.  Errors as spin_trotter_evolve_ex (argument
  * checks), SPIN_ENOMEM if the tables cannot be allocated.
  */
 int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
@@ -237,7 +264,8 @@ int spin_tuned_options(int32_t prec, int32_t M, const spin_coupling *J, int32_t 
 /*
  * Introspection of the execution plan (host only: no device work, usable
  * without a GPU).  The plan is what spin_trotter_evolve_ex would run for the
- * same arguments.
+ * same arguments, or spin_trotter_evolve_profile with observed_site =
+ * SPIN_ALL_SITES.
  */
 typedef struct {
     int32_t path;           /* 0 = one pass per factor, 1 = whole state in one workgroup,
@@ -263,7 +291,7 @@ int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t 
  * spin_plan_trace -- the op sequence the plan applies, in execution order,
  * as records of 5 doubles: a factor exp(-i(A I^z_i I^z_j + (B/2)(I^+_i I^-_j +
  * I^-_i I^+_j))) is (0, i, j, A, B) (A, B = strengths times time, merged
- * factors summed); an observable of step k is (1, k, 0, 0, 0).
+ * factors summed); an observable of site n' after step k is (1, k, n', 0, 0).
  *   buf, cap : host buffer of cap records (may be NULL with cap = 0).
  *   len      : number of records of the full trace (always written).
  * Returns SPIN_OK even when cap < *len (the buffer then holds a prefix).

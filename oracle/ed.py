@@ -22,7 +22,8 @@
   a) of the coupling-network section): for a chain with site 0 at one end,
   P(t) = |[g(t)]_00|^2 with g the single-particle propagator, exp(-i h t)
   for the exact dynamics or the Strang product of 2x2 bond rotations for
-  the Trotterised one.
+  the Trotterised one; ``free_fermion_profile`` gives |[g]_s0|^2 at every
+  chain site s (the polarisation profile).
 """
 from __future__ import annotations
 
@@ -142,6 +143,14 @@ def free_fermion_P(L: int, bonds, times=None, dt=None, n_steps=None):
             g = (v * np.exp(-1j * w * t)) @ v.T
             out.append(abs(g[0, 0]) ** 2)
         return np.array(out)
+    return free_fermion_profile(L, bonds, dt, n_steps)[:, 0]
+
+
+def free_fermion_profile(L: int, bonds, dt: float, n_steps: int) -> np.ndarray:
+    """|[g_k]_s0|^2 for every chain site s after k Strang steps, shape
+    (n_steps+1, L): the polarisation profile of an XY chain whose site 0
+    starts polarised (infinite-temperature ensemble).  g_k = u^k with u the
+    Strang product of the bonds' 2x2 rotations, in the many-body order."""
     tau = 0.5 * dt
     u = np.eye(L, dtype=np.complex128)
     for (l, m, b) in list(bonds) + list(bonds)[::-1]:
@@ -151,8 +160,8 @@ def free_fermion_P(L: int, bonds, times=None, dt=None, n_steps=None):
         r[l, m] = r[m, l] = -1j * np.sin(t)
         u = r @ u
     g = np.eye(L, dtype=np.complex128)
-    out = [1.0]
+    out = [np.abs(g[:, 0]) ** 2]
     for _ in range(n_steps):
         g = u @ g
-        out.append(abs(g[0, 0]) ** 2)
+        out.append(np.abs(g[:, 0]) ** 2)
     return np.array(out)

@@ -19,6 +19,7 @@ import numpy as np
 __all__ = [
     "SPIN_C64", "SPIN_C128", "SpinError", "library_path", "load_library",
     "spin_init_random_phase", "spin_trotter_evolve", "spin_trotter_evolve_ex",
+    "spin_trotter_evolve_profile", "SPIN_ALL_SITES",
     "spin_local_polarization", "spin_trotter_evolve_batch", "spin_describe_plan",
     "spin_plan_trace", "spin_last_error", "spin_release_caches", "spin_version",
     "Options", "Problem",
@@ -27,6 +28,7 @@ __all__ = [
 SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EHIP, SPIN_EUNSUPPORTED, SPIN_ENOTFOUND = 0, -1, -2, -3, -4, -5
 SPIN_C64, SPIN_C128 = 1, 2
 SPIN_INIT_NONE, SPIN_INIT_RANDOM_PHASE, SPIN_INIT_BASIS = 0, 1, 2
+SPIN_ALL_SITES = -1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "libspinqp.so")
@@ -97,6 +99,7 @@ def load_library():
     lib.spin_init_random_phase.argtypes = [vp, i32, i32, i32, u64, vp]
     lib.spin_trotter_evolve.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, vp]
     lib.spin_trotter_evolve_ex.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, op, vp]
+    lib.spin_trotter_evolve_profile.argtypes = [vp, i32, i32, cp, i32, dbl, i64, vp, vp, op, vp]
     lib.spin_local_polarization.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.spin_trotter_evolve_batch.argtypes = [ctypes.POINTER(Problem), i32, cp, i64, i32, dbl,
                                               i64, i32, vp]
@@ -113,6 +116,7 @@ def load_library():
     lib.spin_version.restype = ctypes.c_char_p
     lib.spin_release_caches.restype = None
     for name in ("spin_init_random_phase", "spin_trotter_evolve", "spin_trotter_evolve_ex",
+                 "spin_trotter_evolve_profile",
                  "spin_local_polarization", "spin_trotter_evolve_batch", "spin_prepare_plan",
                  "spin_describe_plan", "spin_plan_trace", "spin_autotune", "spin_tuned_options"):
         getattr(lib, name).restype = ctypes.c_int
@@ -201,6 +205,20 @@ def spin_trotter_evolve(psi, M: int, couplings, dt: float, n_steps: int, observe
                         P, N=None, stream=None) -> None:
     """n_steps symmetric Trotter steps of ``psi`` in place; P[k], N[k] (FP64)."""
     spin_trotter_evolve_ex(psi, M, couplings, dt, n_steps, observed_site, P, N, None, stream)
+
+
+def spin_trotter_evolve_profile(psi, M: int, couplings, dt: float, n_steps: int, Pall, N=None,
+                                options: Optional[Options] = None, stream=None) -> None:
+    """n_steps steps of ``psi`` in place with every site's polarisation after
+    every step: Pall[k*M + n'] (FP64, (n_steps+1)*M entries), N[k]."""
+    lib = load_library()
+    p, prec = _state(psi, M)
+    arr, K = _couplings(couplings)
+    _check(lib.spin_trotter_evolve_profile(p, prec, M, arr, K, float(dt), int(n_steps),
+                                           _f64(Pall, (n_steps + 1) * M, "Pall"),
+                                           _f64(N, n_steps + 1, "N"),
+                                           ctypes.byref(options) if options is not None else None,
+                                           _stream(stream)))
 
 
 def spin_local_polarization(psi, M: int, site: int, out, stream=None) -> None:

@@ -110,14 +110,14 @@ int scratch_get(hipStream_t st, size_t bytes, void** out) {
 
 // ------------------------------------------------------------- plan cache
 struct PlanKey {
-    int dev, prec, M, observed, k, r, nt, c, merge, engine;
+    int dev, prec, M, observed, k, r, nt, c, merge, engine, profile;
     double dt;
     int64_t n_steps;
     std::vector<double> J;    // flattened couplings
     bool operator<(const PlanKey& o) const {
-        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, engine, dt, n_steps, J) <
+        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, engine, profile, dt, n_steps, J) <
                std::tie(o.dev, o.prec, o.M, o.observed, o.k, o.r, o.nt, o.c, o.merge, o.engine,
-                        o.dt, o.n_steps, o.J);
+                        o.profile, o.dt, o.n_steps, o.J);
     }
 };
 
@@ -135,8 +135,10 @@ struct DevicePlan {
     // resident
     int res_r = 0, res_nt = 0;
     int pro_stage0 = 0, pro_nstage = 0, step_stage0 = 0, step_nstage = 0;
-    // per template: measurement steps (relative)
+    // per template: measurement steps (relative) and their sites
     std::vector<std::vector<int64_t>> meas;
+    std::vector<std::vector<int>> meas_site;
+    bool profile = false;
     size_t stages_total = 0;
     ~DevicePlan() {
         if (d_passes) (void)hipFree(d_passes);
@@ -207,13 +209,13 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
         if (sh.resident) {
             dp->resident = true;
             res_shape(key.prec, key.M, &dp->res_r, &dp->res_nt);
-            ResidentPlan rp = plan_resident(key.M, J, key.dt, key.observed, key.merge != 0, dp->res_r);
-            const int nthreads = 1 << std::max(0, key.M - dp->res_r);
+            ResidentPlan rp = plan_resident(key.M, J, key.dt, key.observed, key.merge != 0, dp->res_r,
+                                            key.profile != 0);
             dp->pro_stage0 = 0;
-            encode_pass<T>(rp.prologue, key.M, key.observed, tb, true);
+            encode_pass<T>(rp.prologue, key.M, key.observed, tb, true, 0, key.profile != 0);
             dp->pro_nstage = int(tb.stages.size());
             dp->step_stage0 = int(tb.stages.size());
-            encode_pass<T>(rp.step, key.M, key.observed, tb, true);
+            encode_pass<T>(rp.step, key.M, key.observed, tb, true, 0, key.profile != 0);
             dp->step_nstage = int(tb.stages.size()) - dp->step_stage0;
             dp->stages_total = tb.stages.size();
         } else {
@@ -221,9 +223,13 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             pp.k = sh.k;
             pp.r = sh.r;
             pp.c = sh.c;
+            pp.profile = key.profile != 0;
+            if (pp.profile) pp.max_meas = kMaxMeasProfile;
             dp->sp = plan_stream_best(key.M, J, key.dt, key.n_steps, key.observed, key.merge != 0, pp);
             dp->shape = PassShape{sh.r, sh.nt};
             dp->shape.engine = sh.engine;
+            dp->shape.profile = pp.profile;
+            dp->profile = pp.profile;
             dp->k = sh.k;
             const int64_t ntiles = int64_t(1) << (key.M - sh.k);
             int dev_cu = 256;
@@ -237,11 +243,16 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             dp->nwg = int(nwg);
             dp->tiles_per_wg = ntiles / nwg;
             for (const HostPass& hp : dp->sp.passes) {
-                encode_pass<T>(hp, key.M, key.observed, tb, false, sh.engine);
+                encode_pass<T>(hp, key.M, key.observed, tb, false, sh.engine, key.profile != 0);
                 std::vector<int64_t> ms;
+                std::vector<int> mst;
                 for (const Op& op : hp.ops)
-                    if (op.kind == 1) ms.push_back(op.step);
+                    if (op.kind == 1) {
+                        ms.push_back(op.step);
+                        mst.push_back(op.i);
+                    }
                 dp->meas.push_back(ms);
+                dp->meas_site.push_back(mst);
             }
             dp->stages_total = tb.stages.size();
         }
@@ -255,8 +266,8 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
 }
 
 int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
-             int observed, const spin_options* opt, std::shared_ptr<DevicePlan>* out,
-             Shape* shape_out) {
+             int observed, const spin_options* opt, bool profile,
+             std::shared_ptr<DevicePlan>* out, Shape* shape_out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     Shape sh = choose_shape(prec, M, opt);
@@ -267,7 +278,8 @@ int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t
         return fail(SPIN_EUNSUPPORTED, os.str());
     }
     PlanKey key{dev, prec, M, observed, sh.k, sh.r, sh.nt, sh.c,
-                (opt && opt->no_merge) ? 0 : 1, sh.resident ? 0 : sh.engine, dt, sh.resident ? 0 : n_steps, {}};
+                (opt && opt->no_merge) ? 0 : 1, sh.resident ? 0 : sh.engine,
+                profile ? 1 : 0, dt, sh.resident ? 0 : n_steps, {}};
     key.J.reserve(J.size() * 4);
     for (const Coupling& c : J) {
         key.J.push_back(c.i);
@@ -296,15 +308,22 @@ int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t
 // ------------------------------------------------------------- evolve
 template <typename T>
 static int evolve_naive(void* psi, int M, const std::vector<Coupling>& J, double dt,
-                        int64_t n_steps, int observed, double* P, double* N, hipStream_t st) {
+                        int64_t n_steps, int observed, double* P, double* N, bool profile,
+                        hipStream_t st) {
     const int nblk = 1024;
     void* scratch = nullptr;
     int rc = scratch_get(st, size_t(nblk) * 2 * sizeof(double), &scratch);
     if (rc) return rc;
     double* part = static_cast<double*>(scratch);
+    // With `profile`, P holds M values per step (row k = every site after k
+    // steps) and N is taken with the observed site's value.
     auto observe = [&](int64_t k) -> int {
-        HIP_TRY((launch_observe<T>(psi, M, observed, part, nblk, st)));
-        HIP_TRY(launch_reduce(part, nblk, 1, 0, 1, P + k, N ? N + k : nullptr, st));
+        for (int site = profile ? 0 : observed; site < (profile ? M : observed + 1); ++site) {
+            double* dstP = profile ? P + k * M + site : P + k;
+            double* dstN = (N && site == observed) ? N + k : nullptr;
+            HIP_TRY((launch_observe<T>(psi, M, site, part, nblk, st)));
+            HIP_TRY(launch_reduce(part, nblk, 1, 0, 1, dstP, dstN, st));
+        }
         return SPIN_OK;
     };
     if ((rc = observe(0))) return rc;
@@ -330,14 +349,82 @@ static int evolve_naive(void* psi, int M, const std::vector<Coupling>& J, double
     return SPIN_OK;
 }
 
+// All-site profile through the fused plan: P is [n_steps + 1][M].  A pass
+// measures some sites of some steps; a step is complete once every site has
+// been measured for it (each site's measurements run in step order), and
+// complete steps are reduced in chunks out of a ring of `ch` step slots.
+template <typename T>
+static int evolve_profile(void* psi, int M, const DevicePlan& dp, int64_t n_steps, double* P,
+                          double* N, hipStream_t st) {
+    if (dp.resident) {
+        ResidentJob job{};
+        job.psi = psi;
+        job.Pall = P;
+        job.N = N;
+        job.M = M;
+        job.init = 0;
+        job.pro_stage0 = dp.pro_stage0;
+        job.pro_nstage = dp.pro_nstage;
+        job.step_stage0 = dp.step_stage0;
+        job.step_nstage = dp.step_nstage;
+        HIP_TRY((launch_resident<T>(dp.res_r, dp.res_nt, job, nullptr, 1,
+                                    static_cast<const DevStage*>(dp.d_stages),
+                                    static_cast<const DevOp<T>*>(dp.d_ops), n_steps, st)));
+        return SPIN_OK;
+    }
+    const int64_t total = n_steps + 1;
+    const int ch = int(std::min<int64_t>(total, 64));
+    void* scratch = nullptr;
+    int rc = scratch_get(st, size_t(ch) * dp.nwg * (M + 1) * sizeof(double), &scratch);
+    if (rc) return rc;
+    double* part = static_cast<double*>(scratch);
+    std::vector<int64_t> next(M, 0);    // per site: steps measured so far
+    int64_t complete = 0, reduced = 0, highest = 0;
+    const size_t nl = dp.sp.launch_tmpl.size();
+    for (size_t l = 0; l < nl; ++l) {
+        const int t = dp.sp.launch_tmpl[l];
+        const int64_t off = dp.sp.launch_offset[l];
+        for (int64_t s : dp.meas[t]) highest = std::max(highest, s + off + 1);
+        if (highest - reduced > ch) {
+            std::ostringstream os;
+            os << "internal: profile measurements run " << highest - reduced
+               << " steps ahead of the reduction (ring of " << ch << ")";
+            return fail(SPIN_EUNSUPPORTED, os.str());
+        }
+        PassShape shp = dp.shape;
+        shp.writes = dp.sp.passes[t].writes;
+        HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp.d_passes),
+                                static_cast<const DevStage*>(dp.d_stages),
+                                static_cast<const DevOp<T>*>(dp.d_ops), t, dp.tiles_per_wg,
+                                dp.nwg, part, off, ch, st)));
+        for (size_t m = 0; m < dp.meas[t].size(); ++m) {
+            int64_t& nx = next[dp.meas_site[t][m]];
+            nx = std::max(nx, dp.meas[t][m] + off + 1);
+        }
+        complete = *std::min_element(next.begin(), next.end());
+        if (complete - reduced >= ch / 2 || (l + 1 == nl && complete > reduced)) {
+            HIP_TRY(launch_reduce_profile(part, dp.nwg, ch, M, reduced, complete - reduced, P, N, st));
+            reduced = complete;
+        }
+    }
+    if (reduced != total) {
+        std::ostringstream os;
+        os << "internal: profile plan measured " << reduced << " of " << total << " steps";
+        return fail(SPIN_EUNSUPPORTED, os.str());
+    }
+    return SPIN_OK;
+}
+
 template <typename T>
 static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double dt,
                         int64_t n_steps, int observed, double* P, double* N,
-                        const spin_options* opt, hipStream_t st) {
+                        const spin_options* opt, bool profile, hipStream_t st) {
     std::shared_ptr<DevicePlan> dp;
     Shape sh;
-    int rc = get_plan(sizeof(T) == 4 ? SPIN_C64 : SPIN_C128, M, J, dt, n_steps, observed, opt, &dp, &sh);
+    int rc = get_plan(sizeof(T) == 4 ? SPIN_C64 : SPIN_C128, M, J, dt, n_steps, observed, opt,
+                      profile, &dp, &sh);
     if (rc) return rc;
+    if (profile) return evolve_profile<T>(psi, M, *dp, n_steps, P, N, st);
     if (dp->resident) {
         ResidentJob job{};
         job.psi = psi;
@@ -428,35 +515,59 @@ int spin_local_polarization(const void* psi, int32_t prec, int32_t M, int32_t si
     return SPIN_OK;
 }
 
-int spin_trotter_evolve_ex(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
-                           double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
-                           double* N_dev, const spin_options* opt, void* stream) {
+}  // extern "C"
+
+namespace spinqp {
+// Shared body of spin_trotter_evolve_ex (one observed site) and
+// spin_trotter_evolve_profile (every site; the norm rides on site 0).
+static int evolve_entry(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                        double dt, int64_t n_steps, int32_t observed_site, bool profile,
+                        double* P_dev, double* N_dev, const spin_options* opt, void* stream) {
     try {
         int rc = validate_common(psi, prec, M);
         if (rc) return rc;
-        if (!P_dev) return fail(SPIN_EINVAL, "P_dev is NULL");
+        if (!P_dev) return fail(SPIN_EINVAL, profile ? "Pall_dev is NULL" : "P_dev is NULL");
         if (!std::isfinite(dt)) return fail(SPIN_EINVAL, "dt is not finite");
         if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
         if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
         if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
         if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
+        if (profile && opt && opt->engine != 0)
+            return fail(SPIN_EUNSUPPORTED, "the all-site profile runs on the butterfly engine only");
         std::vector<Coupling> Jv;
         if ((rc = validate_couplings(M, J, K, &Jv))) return rc;
         hipStream_t st = static_cast<hipStream_t>(stream);
         const bool naive = opt && opt->schedule == 1;
         if (naive) {
-            rc = prec == SPIN_C64 ? evolve_naive<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, st)
-                                  : evolve_naive<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, st);
+            rc = prec == SPIN_C64
+                     ? evolve_naive<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, profile, st)
+                     : evolve_naive<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, profile, st);
         } else {
             rc = prec == SPIN_C64
-                     ? evolve_fused<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, st)
-                     : evolve_fused<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, st);
+                     ? evolve_fused<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, profile, st)
+                     : evolve_fused<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, profile, st);
         }
         if (rc == SPIN_OK) g_err.clear();
         return rc;
     } catch (const std::exception& e) {
         return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());
     }
+}
+}  // namespace spinqp
+
+extern "C" {
+
+int spin_trotter_evolve_ex(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                           double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
+                           double* N_dev, const spin_options* opt, void* stream) {
+    return evolve_entry(psi, prec, M, J, K, dt, n_steps, observed_site, false, P_dev, N_dev, opt,
+                        stream);
+}
+
+int spin_trotter_evolve_profile(void* psi, int32_t prec, int32_t M, const spin_coupling* J,
+                                int32_t K, double dt, int64_t n_steps, double* Pall_dev,
+                                double* N_dev, const spin_options* opt, void* stream) {
+    return evolve_entry(psi, prec, M, J, K, dt, n_steps, 0, true, Pall_dev, N_dev, opt, stream);
 }
 
 int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K, double dt,
@@ -467,9 +578,13 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K
         if (M < 1 || M > maxM) return fail(SPIN_EINVAL, "M out of range");
         if (!std::isfinite(dt)) return fail(SPIN_EINVAL, "dt is not finite");
         if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
+        const bool profile = observed_site == SPIN_ALL_SITES;
+        if (profile) observed_site = 0;
         if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
         if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
         if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
+        if (profile && opt && opt->engine != 0)
+            return fail(SPIN_EUNSUPPORTED, "the all-site profile runs on the butterfly engine only");
         std::vector<Coupling> Jv;
         int rc = validate_couplings(M, J, K, &Jv);
         if (rc) return rc;
@@ -478,7 +593,7 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K
             return SPIN_OK;     // the unfused schedule has no plan
         }
         std::shared_ptr<DevicePlan> dp;
-        rc = get_plan(prec, M, Jv, dt, n_steps, observed_site, opt, &dp, nullptr);
+        rc = get_plan(prec, M, Jv, dt, n_steps, observed_site, opt, profile, &dp, nullptr);
         if (rc == SPIN_OK) g_err.clear();
         return rc;
     } catch (const std::exception& e) {
@@ -515,7 +630,8 @@ int host_args(int32_t prec, int32_t M, const spin_coupling* J, int32_t K, double
     if (M < 1 || M > maxM) return fail(SPIN_EINVAL, "M out of range");
     if (!std::isfinite(dt)) return fail(SPIN_EINVAL, "dt is not finite");
     if (n_steps < 0) return fail(SPIN_EINVAL, "n_steps < 0");
-    if (observed < 0 || observed >= M) return fail(SPIN_EINVAL, "observed_site out of range");
+    if ((observed < 0 || observed >= M) && observed != SPIN_ALL_SITES)
+        return fail(SPIN_EINVAL, "observed_site out of range");
     return validate_couplings(M, J, K, Jv);
 }
 
@@ -525,12 +641,18 @@ struct HostPlan {
     StreamPlan sp;
     ResidentPlan rp;
     int res_r = 0, res_nt = 0;
+    bool profile = false;
 };
 
 int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double dt, int64_t n_steps,
               int32_t observed, const spin_options* opt, HostPlan* hp) {
     if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
     if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
+    const bool profile = observed == SPIN_ALL_SITES;
+    if (profile) observed = 0;
+    if (profile && opt && opt->engine != 0)
+        return fail(SPIN_EUNSUPPORTED, "the all-site profile runs on the butterfly engine only");
+    hp->profile = profile;
     hp->sh = choose_shape(prec, M, opt);
     if (!(opt && opt->schedule == 1) && !hp->sh.resident && !hp->sh.valid)
         return fail(SPIN_EUNSUPPORTED, "no pass kernel for the requested tile shape");
@@ -542,13 +664,15 @@ int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double d
             hp->path = 1;
             const int rmax = prec == SPIN_C64 ? 5 : 4;
             hp->res_r = std::min(rmax, int(M));
-            hp->rp = plan_resident(M, Jv, dt, observed, merge, hp->res_r);
+            hp->rp = plan_resident(M, Jv, dt, observed, merge, hp->res_r, profile);
         } else {
             hp->path = 2;
             PassParams pp;
             pp.k = hp->sh.k;
             pp.r = hp->sh.r;
             pp.c = hp->sh.c;
+            pp.profile = profile;
+            if (profile) pp.max_meas = kMaxMeasProfile;
             hp->sp = plan_stream_best(M, Jv, dt, n_steps, observed, merge, pp);
         }
     } catch (const std::exception& e) {
@@ -627,17 +751,21 @@ extern "C" int spin_plan_trace(int32_t prec, int32_t M, const spin_coupling* J, 
         for (const HostStage& s : p.stages)
             for (int o : s.ops) {
                 const Op& op = p.ops[o];
-                if (op.kind == 1) put(1, double(op.step + off), 0, 0, 0);
+                if (op.kind == 1) put(1, double(op.step + off), op.i, 0, 0);
                 else put(0, op.i, op.j, op.A, op.B);
             }
     };
     if (hp.path == 0) {
         const double tau = 0.5 * dt;
-        put(1, 0, 0, 0, 0);
+        auto observe = [&](int64_t k) {
+            if (!hp.profile) put(1, double(k), observed_site, 0, 0);
+            else for (int s = 0; s < M; ++s) put(1, double(k), s, 0, 0);
+        };
+        observe(0);
         for (int64_t k = 1; k <= n_steps; ++k) {
             for (size_t g = 0; g < Jv.size(); ++g) put(0, Jv[g].i, Jv[g].j, Jv[g].a * tau, Jv[g].b * tau);
             for (size_t g = Jv.size(); g-- > 0;) put(0, Jv[g].i, Jv[g].j, Jv[g].a * tau, Jv[g].b * tau);
-            put(1, double(k), 0, 0, 0);
+            observe(k);
         }
     } else if (hp.path == 1) {
         put_pass(hp.rp.prologue, 0);

@@ -17,6 +17,7 @@ constexpr int kMaxRegBits = 6;      // at most 64 amplitudes per lane
 constexpr int kMaxMeas = 4;         // observable slots one pass can hold
 constexpr int kMaxSites = 40;
 constexpr int kBatchRing = 16;      // observable slots per gang problem (steps mod 16)
+constexpr int kMaxMeasProfile = 16; // per-site observables one pass can hold (all-site profile)
 
 // Op codes.  A two-spin factor on register bits (qa < qb) of a stage has
 // code qa*8 + qb; kOpZZ is or-ed in when the factor carries an I^z I^z
@@ -37,7 +38,11 @@ constexpr int kMatFloats = 64 * 64;
 //   theta = B/2, t = tan(theta/2), s = sin(theta)     (three-shear rotation)
 //   (pr, pi) = exp(+i A/4)                             (anti-aligned phase)
 // For kOpMeas, aux is the measurement slot of the pass (resident kernels:
-// unused).
+// unused).  In all-site profile plans every site has its own kOpMeas and
+// aux = slot | kind << 6 | index << 8 | (norm slot + 1) << 14 | site << 17:
+// the site's bit is thread bit `index` of the stage (kind 0), register bit
+// `index` (kind 1) or global address bit `index` of the tile base (kind 2);
+// norm slot + 1 = 0 when this observable does not also carry the norm.
 template <typename T>
 struct DevOp {
     int32_t code;
@@ -75,6 +80,11 @@ struct DevPass {
     int64_t free_mask;        // mask of the global bits not in the tile
     int32_t tbit[16];         // global bit of tile-local position p (input layout)
     int32_t tbit_out[16];     // global bit of tile-local position p (output layout)
+    // All-site profile plans: per-site measurement slots and norm slots.
+    int32_t pmeas, pnorm;
+    int64_t pmeas_step[kMaxMeasProfile];   // step label of slot m
+    int8_t pmeas_site[kMaxMeasProfile];    // site of slot m
+    int32_t pnorm_meas[kMaxMeas];          // measurement slot whose step the norm slot carries
 };
 
 // Fixed LDS swizzle of the one-workgroup kernel (tiled passes use a layout

@@ -110,6 +110,39 @@ __device__ __forceinline__ void block_sum2(double& p, double& n, double* red) {
     __syncthreads();
 }
 
+// Workgroup sum of v (result valid in thread 0).
+template <int NT>
+__device__ __forceinline__ double block_sum1(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (NT + 63) / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// Profile partials [slot][nwg][M + 1] -> Pall[s * M + site], N[s]; one
+// workgroup per (step, site or norm).
+__global__ __launch_bounds__(256) void k_reduce_profile(const double* __restrict__ partials, int nwg,
+                                                        int ch, int M, int64_t s0,
+                                                        double* __restrict__ Pall,
+                                                        double* __restrict__ N) {
+    __shared__ double red[8];
+    const int64_t s = s0 + blockIdx.x / (M + 1);
+    const int site = int(blockIdx.x % (M + 1));
+    const double* src = partials + (size_t)(s % ch) * nwg * (M + 1);
+    double v = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += 256) v += src[(size_t)w * (M + 1) + site];
+    v = block_sum1<256>(v, red);
+    if (threadIdx.x == 0) {
+        if (site < M) Pall[s * M + site] = v;
+        else if (N) N[s] = v;
+    }
+}
+
 // partials: [slot][nwg][2]; P/N for steps s0..s1-1, slot = s % ch.
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int nwg, int ch,
                                                 int64_t s0, double* __restrict__ P,
@@ -440,13 +473,38 @@ __device__ __forceinline__ int64_t lane_offset(const int64_t* gt, int tid) {
     return o;
 }
 
-template <typename T, int R, int NT, bool WRITES, int ENGINE = 0>
+// All-site profile accumulators of a lane: slot m of the pass's per-site
+// observables, and the norm slots.
+struct ProfAcc {
+    double p[kMaxMeasProfile];
+    double n[kMaxMeas];
+};
+
+// One per-site observable (profile kOpMeas) of the lane's registers: the
+// sign of each amplitude follows the site's bit (thread bit, register bit or
+// a bit of the tile base).
+template <int R, typename C>
+__device__ __forceinline__ void prof_observe(const C (&v)[1 << R], int aux, int64_t base,
+                                             double& p, double& n, int& slot, int& nslot) {
+    slot = aux & 63;
+    const int kind = (aux >> 6) & 3, idx = (aux >> 8) & 63;
+    nslot = ((aux >> 14) & 7) - 1;
+    const int sign = kind == 0 ? ((int(threadIdx.x) >> idx) & 1)
+                   : kind == 2 ? int((base >> idx) & 1) : 0;
+    const int mask = kind == 1 ? (1 << idx) : 0;
+    p = 0.0;
+    n = 0.0;
+    reg_observe<R>(v, sign, mask, p, n);
+}
+
+template <typename T, int R, int NT, bool WRITES, int ENGINE = 0, bool PROFILE = false>
 __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, const DevPass& P,
                                            const DevStage* __restrict__ stages,
                                            const DevOp<T>* __restrict__ ops, unsigned wperm,
                                            unsigned G, int64_t tiles_per_member, char* ldsb,
                                            double (&accP)[kMaxMeas], double (&accN)[kMaxMeas],
-                                           const float* __restrict__ mats = nullptr) {
+                                           const float* __restrict__ mats = nullptr,
+                                           ProfAcc* prof = nullptr) {
     using C = typename CT<T>::c;
     const int tid = threadIdx.x;
     const DevStage& S0 = stages[P.stage0];
@@ -496,12 +554,24 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                     o = run_factors<R>(v, ops, o, o1);
                 }
                 if (o < o1) {    // observable of the state at this point
-                    const int slot = ops[o].aux;
-                    double p = 0.0, n = 0.0;
-                    reg_observe<R>(v, sign, S.obs_mask, p, n);
+                    if constexpr (PROFILE) {
+                        double p, n;
+                        int slot, nslot;
+                        prof_observe<R>(v, ops[o].aux, base, p, n, slot, nslot);
 #pragma unroll
-                    for (int m = 0; m < kMaxMeas; ++m)
-                        if (m == slot) { accP[m] += p; accN[m] += n; }
+                        for (int m = 0; m < kMaxMeasProfile; ++m)
+                            if (m == slot) prof->p[m] += p;
+#pragma unroll
+                        for (int m = 0; m < kMaxMeas; ++m)
+                            if (m == nslot) prof->n[m] += n;
+                    } else {
+                        const int slot = ops[o].aux;
+                        double p = 0.0, n = 0.0;
+                        reg_observe<R>(v, sign, S.obs_mask, p, n);
+#pragma unroll
+                        for (int m = 0; m < kMaxMeas; ++m)
+                            if (m == slot) { accP[m] += p; accN[m] += n; }
+                    }
                     ++o;
                 }
             }
@@ -533,7 +603,9 @@ __device__ __forceinline__ void slot_sum(const double (&accP)[kMaxMeas],
 }
 
 // --------------------------------------------------------------- k_pass
-template <typename T, int R, int NT, bool WRITES, int ENGINE>
+// partials: [slot][nwg][2] (P, N), or with PROFILE [slot][nwg][M + 1] (P of
+// every site, then N).
+template <typename T, int R, int NT, bool WRITES, int ENGINE, bool PROFILE>
 __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi,
                                              const DevPass* __restrict__ passes,
                                              const DevStage* __restrict__ stages,
@@ -556,6 +628,33 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
     // line.
     const unsigned G = gridDim.x, w = blockIdx.x;
     const unsigned wperm = (G >= 8) ? (w % 8u) * (G / 8u) + w / 8u : w;
+    if constexpr (PROFILE) {
+        ProfAcc prof;
+#pragma unroll
+        for (int m = 0; m < kMaxMeasProfile; ++m) prof.p[m] = 0.0;
+#pragma unroll
+        for (int m = 0; m < kMaxMeas; ++m) prof.n[m] = 0.0;
+        pass_tiles<T, R, NT, WRITES, ENGINE, true>(psi, P, stages, ops, wperm, G, tiles_per_wg,
+                                                   reinterpret_cast<char*>(lds), accP, accN, mats,
+                                                   &prof);
+        const int M = P.k + P.nfree;
+        auto dst = [&](int64_t step) {
+            return partials + ((size_t)((step_offset + step) % ch) * nwg + blockIdx.x) * (M + 1);
+        };
+#pragma unroll
+        for (int m = 0; m < kMaxMeasProfile; ++m) {
+            if (m >= P.pmeas) break;
+            const double v = block_sum1<NT>(prof.p[m], red);
+            if (threadIdx.x == 0) dst(P.pmeas_step[m])[P.pmeas_site[m]] = v;
+        }
+#pragma unroll
+        for (int m = 0; m < kMaxMeas; ++m) {
+            if (m >= P.pnorm) break;
+            const double v = block_sum1<NT>(prof.n[m], red);
+            if (threadIdx.x == 0) dst(P.pmeas_step[P.pnorm_meas[m]])[M] = v;
+        }
+        return;
+    }
     pass_tiles<T, R, NT, WRITES, ENGINE>(psi, P, stages, ops, wperm, G, tiles_per_wg,
                                          reinterpret_cast<char*>(lds), accP, accN, mats);
     for (int m = 0; m < P.nmeas; ++m) {
@@ -574,7 +673,7 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
 // One workgroup owns one whole state (2^M <= NT << R amplitudes) in LDS and
 // runs the prologue stages once and the step stages n_steps times, writing
 // P[k], N[k] itself.
-template <typename T, int R, int NT>
+template <typename T, int R, int NT, bool PROFILE = false>
 __device__ __forceinline__ void resident_run(const ResidentJob& J, const DevStage* __restrict__ stages,
                                              const DevOp<T>* __restrict__ ops, int64_t n_steps,
                                              typename CT<T>::c* lds, double* red) {
@@ -617,14 +716,28 @@ __device__ __forceinline__ void resident_run(const ResidentJob& J, const DevStag
             while (o < o1) {
                 o = run_factors<R>(v, ops, o, o1);
                 if (o < o1) {    // observable: reduce over the workgroup now
-                    double p = 0.0, n = 0.0;
-                    reg_observe<R>(v, sign, S.obs_mask, p, n);
-                    p = act ? p : 0.0;
-                    n = act ? n : 0.0;
-                    block_sum2<NT>(p, n, red);
-                    if (tid == 0) {
-                        J.P[step] = p;
-                        if (J.N) J.N[step] = n;
+                    if constexpr (PROFILE) {
+                        const int aux = ops[o].aux;
+                        double p, n;
+                        int slot, nslot;
+                        prof_observe<R>(v, aux, 0, p, n, slot, nslot);
+                        p = act ? p : 0.0;
+                        n = act ? n : 0.0;
+                        block_sum2<NT>(p, n, red);
+                        if (tid == 0) {
+                            J.Pall[step * M + ((aux >> 17) & 63)] = p;
+                            if (nslot >= 0 && J.N) J.N[step] = n;
+                        }
+                    } else {
+                        double p = 0.0, n = 0.0;
+                        reg_observe<R>(v, sign, S.obs_mask, p, n);
+                        p = act ? p : 0.0;
+                        n = act ? n : 0.0;
+                        block_sum2<NT>(p, n, red);
+                        if (tid == 0) {
+                            J.P[step] = p;
+                            if (J.N) J.N[step] = n;
+                        }
                     }
                     ++o;
                 }
@@ -641,7 +754,7 @@ __device__ __forceinline__ void resident_run(const ResidentJob& J, const DevStag
     __syncthreads();
 }
 
-template <typename T, int R, int NT>
+template <typename T, int R, int NT, bool PROFILE>
 __global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
                                                  const ResidentJob* __restrict__ jobs,
                                                  const DevStage* __restrict__ stages,
@@ -651,7 +764,7 @@ __global__ __launch_bounds__(NT) void k_resident(ResidentJob job0,
     __shared__ C lds[NT << R];
     __shared__ double red[2 * ((NT + 63) / 64)];
     const ResidentJob J = jobs ? jobs[blockIdx.x] : job0;
-    resident_run<T, R, NT>(J, stages, ops, n_steps, lds, red);
+    resident_run<T, R, NT, PROFILE>(J, stages, ops, n_steps, lds, red);
 }
 
 // ---------------------------------------------------------------- k_batch
@@ -818,6 +931,14 @@ hipError_t launch_observe(const void* psi, int M, int site, double* partials, in
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_profile(const double* partials, int nwg, int ch, int M, int64_t s0,
+                                 int64_t count, double* Pall, double* N, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_profile, dim3(unsigned(count * (M + 1))), dim3(256), 0, st, partials,
+                       nwg, ch, M, s0, Pall, N);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* partials, int nwg, int ch, int64_t s0, int64_t count,
                          double* P, double* N, hipStream_t st) {
     if (count <= 0) return hipSuccess;
@@ -836,17 +957,17 @@ hipError_t launch_factor(void* psi, int M, int lo, int hi, double t, double s, d
     return hipGetLastError();
 }
 
-template <typename T, int R, int NT, int ENGINE = 0>
+template <typename T, int R, int NT, int ENGINE = 0, bool PROFILE = false>
 static hipError_t pass_one(bool writes, void* psi, const DevPass* passes, const DevStage* stages,
                            const DevOp<T>* ops, int pass_index, int64_t tiles_per_wg, int nwg,
                            double* partials, int64_t step_offset, int ch, const float* mats,
                            hipStream_t st) {
     if (writes)
-        hipLaunchKernelGGL((k_pass<T, R, NT, true, ENGINE>), dim3(nwg), dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_pass<T, R, NT, true, ENGINE, PROFILE>), dim3(nwg), dim3(NT), 0, st,
                            reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
                            pass_index, tiles_per_wg, partials, step_offset, ch, nwg, mats);
     else
-        hipLaunchKernelGGL((k_pass<T, R, NT, false, ENGINE>), dim3(nwg), dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_pass<T, R, NT, false, ENGINE, PROFILE>), dim3(nwg), dim3(NT), 0, st,
                            reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
                            pass_index, tiles_per_wg, partials, step_offset, ch, nwg, mats);
     return hipGetLastError();
@@ -877,8 +998,12 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
     if (sh.engine != 0) return hipErrorInvalidValue;
 #define SPIN_PASS(RR, NTT)                                                                   \
     if (sh.r == RR && sh.nt == NTT)                                                          \
-        return pass_one<T, RR, NTT>(sh.writes, psi, passes, stages, ops, pass_index, tiles_per_wg, nwg, \
-                                    partials, step_offset, ch, nullptr, st);
+        return sh.profile                                                                    \
+                   ? pass_one<T, RR, NTT, 0, true>(sh.writes, psi, passes, stages, ops, pass_index, \
+                                                   tiles_per_wg, nwg, partials, step_offset, ch,   \
+                                                   nullptr, st)                                    \
+                   : pass_one<T, RR, NTT>(sh.writes, psi, passes, stages, ops, pass_index,          \
+                                          tiles_per_wg, nwg, partials, step_offset, ch, nullptr, st);
     if constexpr (sizeof(T) == 4) {
         SPIN_PASS(5, 256) SPIN_PASS(5, 512) SPIN_PASS(4, 256) SPIN_PASS(6, 256)
         SPIN_PASS(4, 512) SPIN_PASS(4, 1024)
@@ -893,8 +1018,12 @@ template <typename T, int R, int NT>
 static hipError_t res_one(const ResidentJob& job0, const ResidentJob* jobs, int njobs,
                           const DevStage* stages, const DevOp<T>* ops, int64_t n_steps,
                           hipStream_t st) {
-    hipLaunchKernelGGL((k_resident<T, R, NT>), dim3(njobs), dim3(NT), 0, st, job0, jobs, stages,
-                       ops, n_steps);
+    if (!jobs && job0.Pall)    // one problem with the all-site profile
+        hipLaunchKernelGGL((k_resident<T, R, NT, true>), dim3(njobs), dim3(NT), 0, st, job0, jobs,
+                           stages, ops, n_steps);
+    else
+        hipLaunchKernelGGL((k_resident<T, R, NT, false>), dim3(njobs), dim3(NT), 0, st, job0, jobs,
+                           stages, ops, n_steps);
     return hipGetLastError();
 }
 

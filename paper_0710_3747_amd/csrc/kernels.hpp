@@ -13,6 +13,7 @@ struct ResidentJob {
     void* psi;
     double* P;
     double* N;
+    double* Pall;     // all-site profile [step][M] (profile launches only)
     uint64_t seed;
     int32_t M, polarized, init;
     int32_t pro_stage0, pro_nstage, step_stage0, step_nstage;
@@ -44,6 +45,7 @@ struct PassShape {
     bool writes = true;   // false: read-only pass (observables only)
     int engine = 0;       // 0: VALU butterflies; 1: MFMA stage matrices (complex64, r = 5, nt = 512)
     const float* mats = nullptr;   // engine 1: device matrix table
+    bool profile = false;          // per-site observables: profile partials [slot][nwg][M + 1]
 };
 // Whether a pass kernel is instantiated for (precision, r, nt, engine).
 bool pass_shape_exists(bool f32, int r, int nt, int engine);
@@ -55,6 +57,8 @@ hipError_t launch_observe(const void* psi, int M, int site, double* partials, in
                           hipStream_t st);
 hipError_t launch_reduce(const double* partials, int nwg, int ch, int64_t s0, int64_t count,
                          double* P, double* N, hipStream_t st);
+hipError_t launch_reduce_profile(const double* partials, int nwg, int ch, int M, int64_t s0,
+                                 int64_t count, double* Pall, double* N, hipStream_t st);
 template <typename T>
 hipError_t launch_factor(void* psi, int M, int lo, int hi, double t, double s, double pr,
                          double pim, int zz, hipStream_t st);

@@ -14,8 +14,9 @@
 namespace spinqp {
 
 // ------------------------------------------------------------------ sequence
-SeqBuilder::SeqBuilder(int M, const std::vector<Coupling>& J, double dt, int observed, bool merge)
-    : observed_(observed), merge_(merge), dt_(dt), J_(J), last_(M, -1) {}
+SeqBuilder::SeqBuilder(int M, const std::vector<Coupling>& J, double dt, int observed, bool merge,
+                       bool profile)
+    : observed_(observed), merge_(merge), profile_(profile), dt_(dt), J_(J), last_(M, -1) {}
 
 void SeqBuilder::emit_factor(const Coupling& c, double tau, int64_t step) {
     int i = std::min(c.i, c.j), j = std::max(c.i, c.j);
@@ -37,8 +38,15 @@ void SeqBuilder::emit_factor(const Coupling& c, double tau, int64_t step) {
 
 void SeqBuilder::emit_observable(int64_t step) {
     if (step != cur_step_) { cur_step_ = step; idx_ = 0; }
-    ops.push_back(Op{1, observed_, observed_, 0.0, 0.0, step, 1 << 30});
-    last_[observed_] = int(ops.size()) - 1;
+    if (!profile_) {
+        ops.push_back(Op{1, observed_, observed_, 0.0, 0.0, step, 1 << 30});
+        last_[observed_] = int(ops.size()) - 1;
+        return;
+    }
+    for (int s = 0; s < int(last_.size()); ++s) {
+        ops.push_back(Op{1, s, s, 0.0, 0.0, step, (1 << 30) + s});
+        last_[s] = int(ops.size()) - 1;
+    }
 }
 
 void SeqBuilder::emit_step(int64_t step) {
@@ -59,6 +67,7 @@ inline int popc(Mask m) { return __builtin_popcountll(m); }
 
 struct Sched {
     int M, observed, k, max_meas;
+    bool all_sites = false;    // observables on every site (profile)
     const std::vector<Op>& ops;
     std::vector<std::vector<int>> site_ops;
     std::vector<int> pos_i, pos_j;     // index of op in site_ops of its sites
@@ -119,7 +128,7 @@ struct Sched {
             }
         };
         for (int s = 0; s < M; ++s)
-            if ((T & bit(s)) || s == observed) consider(s);
+            if ((T & bit(s)) || s == observed || all_sites) consider(s);
         while (!work.empty()) {
             int n = work.back();
             work.pop_back();
@@ -406,8 +415,9 @@ struct Relabel {
 };
 
 std::vector<Op> gen_sequence(int M, const std::vector<Coupling>& J, double dt, int observed,
-                             bool merge, int64_t s_begin, int64_t s_end, bool initial_obs) {
-    SeqBuilder sb(M, J, dt, observed, merge);
+                             bool merge, int64_t s_begin, int64_t s_end, bool initial_obs,
+                             bool profile) {
+    SeqBuilder sb(M, J, dt, observed, merge, profile);
     if (initial_obs) sb.emit_observable(0);
     for (int64_t s = s_begin; s <= s_end; ++s) sb.emit_step(s);
     return sb.ops;
@@ -624,18 +634,28 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
     const int k = std::min(pp.k, M);
     Mask forced = 0;
     for (int s = 0; s < std::min(pp.c, k); ++s) forced |= bit(s);
-    HostPass obs;
-    for (int s = 0; s < k; ++s) obs.sites.push_back(s);
-    obs.bit_in = obs.sites;
-    obs.bit_out = obs.sites;
-    obs.layout.resize(M);
-    for (int s = 0; s < M; ++s) obs.layout[s] = s;
-    obs.ops.push_back(Op{1, observed, observed, 0, 0, 0, 1 << 30});
-    obs.writes = false;
-    plan.passes.push_back(obs);
-    SeqBuilder sb(M, J, dt, observed, merge);
+    // read-only passes for the step-0 observables (one per site with the
+    // profile, at most max_meas per pass)
+    SeqBuilder sb0(M, J, dt, observed, merge, pp.profile);
+    sb0.emit_observable(0);
+    int nobs0 = 0;
+    for (size_t o = 0; o < sb0.ops.size(); o += size_t(pp.max_meas)) {
+        HostPass obs;
+        for (int s = 0; s < k; ++s) obs.sites.push_back(s);
+        obs.bit_in = obs.sites;
+        obs.bit_out = obs.sites;
+        obs.layout.resize(M);
+        for (int s = 0; s < M; ++s) obs.layout[s] = s;
+        for (size_t q = o; q < std::min(sb0.ops.size(), o + size_t(pp.max_meas)); ++q)
+            obs.ops.push_back(sb0.ops[q]);
+        obs.writes = false;
+        plan.passes.push_back(obs);
+        ++nobs0;
+    }
+    SeqBuilder sb(M, J, dt, observed, merge, pp.profile);
     sb.emit_step(1);
     Sched sc(M, observed, k, pp.max_meas, sb.ops);
+    sc.all_sites = pp.profile;
     sc.window = pp.window;
     sc.rotate = pp.rotate;
     while (!sc.all_done()) {
@@ -644,15 +664,17 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
         plan.passes.push_back(make_pass(sb.ops, ap, T, M));
     }
     for (auto& p : plan.passes) plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c);
-    plan.launch_tmpl.push_back(0);
-    plan.launch_offset.push_back(0);
+    for (int t = 0; t < nobs0; ++t) {
+        plan.launch_tmpl.push_back(t);
+        plan.launch_offset.push_back(0);
+    }
     for (int64_t st = 0; st < n_steps; ++st)
-        for (size_t t = 1; t < plan.passes.size(); ++t) {
+        for (size_t t = size_t(nobs0); t < plan.passes.size(); ++t) {
             plan.launch_tmpl.push_back(int(t));
             plan.launch_offset.push_back(st);
         }
     plan.period_steps = 1;
-    plan.period_passes = int(plan.passes.size()) - 1;
+    plan.period_passes = int(plan.passes.size()) - nobs0;
     return plan;
 }
 
@@ -725,8 +747,9 @@ int add_templates(StreamPlan& plan, std::vector<HostPass>&& passes) {
 std::vector<HostPass> plan_block(int M, const std::vector<Coupling>& J, double dt, int observed,
                                  bool merge, const PassParams& pp, int64_t n, bool initial_obs) {
     const int k = std::min(pp.k, M), c = std::min(pp.c, k);
-    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, n, initial_obs);
+    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, n, initial_obs, pp.profile);
     Sched sc(M, observed, k, pp.max_meas, ops);
+    sc.all_sites = pp.profile;
     sc.window = pp.window;
     sc.rotate = pp.rotate;
     Relabel rl(M, c);
@@ -780,8 +803,9 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
     const int k = std::min(pp.k, M);
     const int c = std::min(pp.c, k);
     const int64_t kSafe = 8;     // steps kept between the frontier and the end
-    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, kGen, true);
+    std::vector<Op> ops = gen_sequence(M, J, dt, observed, merge, 1, kGen, true, pp.profile);
     Sched sc(M, observed, k, pp.max_meas, ops);
+    sc.all_sites = pp.profile;
     sc.window = pp.window;
     sc.rotate = pp.rotate;
     Relabel rl(M, c);
@@ -847,8 +871,9 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
     // regenerate from an odd step so merged ops keep their identities
     int64_t gen_from = std::max<int64_t>(1, base_t - 2);
     if (gen_from % 2 == 0) --gen_from;
-    std::vector<Op> tops = gen_sequence(M, J, dt, observed, merge, gen_from, n_steps, false);
+    std::vector<Op> tops = gen_sequence(M, J, dt, observed, merge, gen_from, n_steps, false, pp.profile);
     Sched tc(M, observed, k, pp.max_meas, tops);
+    tc.all_sites = pp.profile;
     tc.window = pp.window;
     tc.rotate = pp.rotate;
     Relabel tl(M, c);
@@ -954,7 +979,7 @@ StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, in
 
 // --------------------------------------------------------------- resident
 ResidentPlan plan_resident(int M, const std::vector<Coupling>& J, double dt, int observed,
-                           bool merge, int r) {
+                           bool merge, int r, bool profile) {
     ResidentPlan rp;
     rp.prologue.sites.resize(M);
     rp.step.sites.resize(M);
@@ -963,9 +988,11 @@ ResidentPlan plan_resident(int M, const std::vector<Coupling>& J, double dt, int
         hp->bit_in = hp->bit_out = hp->sites;
         hp->layout = hp->sites;
     }
-    rp.prologue.ops.push_back(Op{1, observed, observed, 0, 0, 0, 0});
+    SeqBuilder sb0(M, J, dt, observed, merge, profile);
+    sb0.emit_observable(0);
+    rp.prologue.ops = sb0.ops;
     rp.prologue.writes = false;
-    SeqBuilder sb(M, J, dt, observed, merge);
+    SeqBuilder sb(M, J, dt, observed, merge, profile);
     sb.emit_step(1);
     rp.step.ops = sb.ops;
     rp.step.writes = true;
@@ -1152,7 +1179,7 @@ struct StageMatrix {
 
 template <typename T>
 void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, bool fixed_swizzle,
-                 int engine) {
+                 int engine, bool profile) {
     const int k = int(hp.sites.size());
     constexpr int eb = sizeof(T) * 2;
     DevPass dp{};
@@ -1255,6 +1282,35 @@ void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, boo
         };
         for (int n : hs.ops) {
             const Op& op = hp.ops[n];
+            if (op.kind == 1 && profile) {
+                flush();
+                if (dp.pmeas >= kMaxMeasProfile) throw std::runtime_error("encode: too many observables");
+                const int site = op.i, slot = dp.pmeas++;
+                int kind = 2, index = hp.layout[site];
+                if (local[site] >= 0) {
+                    kind = 0;
+                    for (int t = 0; t < ds.ntb; ++t)
+                        if (tq[t] == local[site]) index = t;
+                    for (int b = 0; b < rr; ++b)
+                        if (hs.regs[b] == local[site]) {
+                            kind = 1;
+                            index = b;
+                        }
+                }
+                int nslot = -1;
+                if (site == observed) {
+                    if (dp.pnorm >= kMaxMeas) throw std::runtime_error("encode: too many norms");
+                    nslot = dp.pnorm++;
+                    dp.pnorm_meas[nslot] = slot;
+                }
+                DevOp<T> d{};
+                d.code = kOpMeas;
+                d.aux = slot | (kind << 6) | (index << 8) | ((nslot + 1) << 14) | (site << 17);
+                dp.pmeas_step[slot] = op.step;
+                dp.pmeas_site[slot] = int8_t(site);
+                out.ops.push_back(d);
+                continue;
+            }
             if (op.kind == 1) {
                 flush();
                 if (nmeas >= kMaxMeas) throw std::runtime_error("encode: too many observables");
@@ -1299,8 +1355,8 @@ void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, boo
     out.passes.push_back(dp);
 }
 
-template void encode_pass<float>(const HostPass&, int, int, DevTables<float>&, bool, int);
-template void encode_pass<double>(const HostPass&, int, int, DevTables<double>&, bool, int);
+template void encode_pass<float>(const HostPass&, int, int, DevTables<float>&, bool, int, bool);
+template void encode_pass<double>(const HostPass&, int, int, DevTables<double>&, bool, int, bool);
 
 std::string describe_plan(const StreamPlan& plan) {
     std::ostringstream os;

@@ -35,7 +35,11 @@ struct Op {
 // Emits the merged op sequence step by step.
 class SeqBuilder {
   public:
-    SeqBuilder(int M, const std::vector<Coupling>& J, double dt, int observed, bool merge);
+    // profile: the observable of a step is one op per site (site s, step k:
+    // the polarisation of site s), each ordered only against that site's
+    // factors.
+    SeqBuilder(int M, const std::vector<Coupling>& J, double dt, int observed, bool merge,
+               bool profile = false);
     void emit_observable(int64_t step);
     void emit_step(int64_t step);   // forward + reverse factors, then observable(step)
     std::vector<Op> ops;
@@ -44,6 +48,7 @@ class SeqBuilder {
     void emit_factor(const Coupling& c, double tau, int64_t step);
     int observed_;
     bool merge_;
+    bool profile_;
     double dt_;
     std::vector<Coupling> J_;
     std::vector<int> last_;    // per site: index of the last op touching it, or -1
@@ -71,6 +76,7 @@ struct PassParams {
     int r = 5;                 // register bits
     int c = 4;                 // low global bits every tile must contain
     int max_meas = kMaxMeas;
+    bool profile = false;      // observables of every site (max_meas kMaxMeasProfile)
     // Scheduling variant (plan_stream tries several and keeps the cheapest
     // by the cost model below):
     int window = 3;            // steps a pass may run ahead of the oldest pending op
@@ -135,7 +141,7 @@ struct ResidentPlan {
     HostPass step;
 };
 ResidentPlan plan_resident(int M, const std::vector<Coupling>& J, double dt, int observed,
-                           bool merge, int r);
+                           bool merge, int r, bool profile = false);
 
 // Encoded device tables.
 template <typename T>
@@ -150,9 +156,10 @@ struct DevTables {
 // tables.  fixed_swizzle: use the one-workgroup kernel's fixed LDS swizzle
 // instead of a layout searched for this pass.  engine 1: the factors of each
 // stage (between observables) become one kOpMat (needs 5 register bits).
+// profile: observables of every site, each with its own slot (see kOpMeas).
 template <typename T>
 void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out,
-                 bool fixed_swizzle = false, int engine = 0);
+                 bool fixed_swizzle = false, int engine = 0, bool profile = false);
 
 std::string describe_plan(const StreamPlan& plan);
 

@@ -50,3 +50,18 @@ def assert_state_close(got, want, prec):
     scale = np.abs(want).max()
     err = np.abs(got - want).max() / scale
     assert err < TOL_PSI[prec], f"state rel err {err:.3e}"
+
+
+def gpu_profile(prec, M, J, dt, steps, polarized=0, seed=1, opts=None, psi0=None):
+    """All-site profile through spin_trotter_evolve_profile.
+
+    Returns (Pall (steps+1, M), N, psi_numpy)."""
+    import torch
+    psi = gpu_state(prec, M, polarized, seed, psi0)
+    Pall = torch.full(((steps + 1) * M,), float("nan"), dtype=torch.float64, device="cuda")
+    N = torch.full((steps + 1,), float("nan"), dtype=torch.float64, device="cuda")
+    o = spq.Options(**opts) if opts else None
+    spq.spin_trotter_evolve_profile(psi, M, J, dt, steps, Pall, N, o)
+    torch.cuda.synchronize()
+    return (Pall.cpu().numpy().reshape(steps + 1, M), N.cpu().numpy(),
+            psi.cpu().numpy().astype(np.complex128))

@@ -191,3 +191,47 @@ def test_mfma_engine_ladder_2x15_sectors_and_vs_butterflies():
     P0, _, _, _ = gpu_evolve(C64, M, J, dt, steps, 0, seed=5, keep_state=False)
     assert np.abs(P1 - P0).max() < 1e-5
     assert np.abs(N1 - 1).max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_profile_ladder_2x15_free_fermions_every_site(prec):
+    """All-site profile at M = 30 on the benchmark's plan shape (rungs at
+    b = 0): the sites of site 0's leg follow |g_s0|^2 of the Trotterised
+    single-particle propagator within the random-phase deviation, the other
+    leg stays at zero within it, the total polarisation is conserved, and the
+    last row equals spin_local_polarization of the final state."""
+    import torch
+    from gpu_helpers import gpu_profile
+    L, dt, steps = 15, 0.05, 100
+    M = 2 * L
+    J = workloads.ladder(L, bx=1.0, by=0.0)
+    note("profile free fermion M=30", prec)
+    Pall, N, _ = gpu_profile(prec, M, J, dt, steps, 0, 5)
+    bonds = [(i, j, b) for (i, j, a, b) in J if i < L and j < L]
+    want = ed.free_fermion_profile(L, bonds, dt, steps)
+    sigma = 2.0 ** (-(M - 1) / 2)
+    assert np.abs(Pall[:, :L] - want).max() < 12 * sigma
+    assert np.abs(Pall[:, L:]).max() < 12 * sigma
+    tol = 1e-10 if prec == C128 else 1e-4
+    assert np.abs(Pall.sum(axis=1) - 1.0).max() < tol
+    assert np.abs(N - 1.0).max() < tol
+    torch.cuda.empty_cache()
+
+
+def test_profile_last_row_is_final_state_M30():
+    import torch
+    M, dt, steps = 30, 0.05, 7
+    J = workloads.ladder(15)
+    note("profile last row M=30")
+    psi = torch.empty(2 ** M, dtype=torch.complex64, device="cuda")
+    spq.spin_init_random_phase(psi, M, 0, 9)
+    Pall = torch.zeros((steps + 1) * M, dtype=torch.float64, device="cuda")
+    spq.spin_trotter_evolve_profile(psi, M, J, dt, steps, Pall, None)
+    out = torch.zeros(2 * M, dtype=torch.float64, device="cuda")
+    for s in range(M):
+        spq.spin_local_polarization(psi, M, s, out[2 * s:])
+    torch.cuda.synchronize()
+    last = Pall.cpu().numpy().reshape(steps + 1, M)[-1]
+    assert np.abs(last - out.cpu().numpy()[0::2]).max() < 1e-9
+    del psi
+    torch.cuda.empty_cache()

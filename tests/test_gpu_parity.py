@@ -395,3 +395,47 @@ def test_basis_init_on_the_gang_path():
         Pw, _, psiw = oracle.trotter_run(psi0, M, J, dt, steps, 3)
         assert np.abs(pr["P"].cpu().numpy() - Pw).max() < TOL_P[C128]
         assert_state_close(pr["psi"].cpu().numpy(), psiw, C128)
+
+
+# ------------------------------------------------------------ all-site profile
+PROFILE = [
+    # name, M, couplings, dt, steps, polarised site, options
+    ("resident-ladder10", 10, workloads.ladder(5), 0.05, 30, 0, {}),
+    ("resident-star9-zz", 9, workloads.star(9, 3, a_over_b=-2.0), 0.07, 12, 4, {}),
+    ("tiled-ladder16-k12", 16, workloads.ladder(8), 0.05, 12, 0, {"tile_bits": 12}),
+    ("tiled-ladder18-long", 18, workloads.ladder(9), 0.05, 60, 0, {}),
+    ("tiled-star15-r4", 15, workloads.star(15, 8, a_over_b=1.0), 0.02, 5, 7,
+     {"tile_bits": 12, "reg_bits": 4}),
+    ("tiled-chain17", 17, workloads.chain(17), 0.1, 20, 0, {}),
+    ("unfused-ladder8", 8, workloads.ladder(4), 0.1, 4, 0, {"schedule": 1}),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", PROFILE, ids=[c[0] for c in PROFILE])
+def test_profile_matches_oracle(prec, case):
+    """Every site's polarisation after every step, element by element against
+    the oracle's profile loop, plus the norm and the final state."""
+    from gpu_helpers import gpu_profile
+    name, M, J, dt, steps, pol, opts = case
+    note("profile", name, prec)
+    Pg, Ng, psig = gpu_profile(prec, M, J, dt, steps, pol, 7, opts)
+    Pw, Nw, psiw = oracle.trotter_profile(oracle.random_phase_state(M, pol, 7), M, J, dt, steps)
+    assert np.abs(Pg - Pw).max() < TOL_P[prec]
+    assert np.abs(Ng - Nw).max() < TOL_P[prec]
+    assert_state_close(psig, psiw, prec)
+
+
+def test_profile_rejects_matrix_engine_and_null_output():
+    import torch
+    psi = gpu_state(C64, 16)
+    P = torch.zeros(17 * 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(spq.SpinError) as e:
+        spq.spin_trotter_evolve_profile(psi, 16, workloads.ladder(8), 0.1, 2, P, None,
+                                        spq.Options(engine=1))
+    assert e.value.code == spq.SPIN_EUNSUPPORTED
+    lib = spq.load_library()
+    arr, K = spq._couplings(workloads.ladder(8))
+    rc = lib.spin_trotter_evolve_profile(psi.data_ptr(), C64, 16, arr, K, 0.1, 2, None, None,
+                                         None, None)
+    assert rc == spq.SPIN_EINVAL and "Pall" in spq.spin_last_error()

@@ -115,6 +115,64 @@ def test_plan_trace_realises_strang_product(case):
     assert np.abs(psit - psiw).max() < 1e-11
 
 
+PROFILE_CASES = [
+    ("ladder10-resident", spq.SPIN_C64, 10, workloads.ladder(5), 0.05, 30, {}),
+    ("star9-zz-resident", spq.SPIN_C128, 9, workloads.star(9, 3, a_over_b=-2.0), 0.07, 12, {}),
+    ("ladder16-k12", spq.SPIN_C128, 16, workloads.ladder(8), 0.05, 12, {"tile_bits": 12}),
+    ("ladder18-k14-long", spq.SPIN_C64, 18, workloads.ladder(9), 0.05, 70, {}),
+    ("star15-k12", spq.SPIN_C64, 15, workloads.star(15, 8, a_over_b=1.0), 0.02, 5,
+     {"tile_bits": 12, "reg_bits": 4}),
+    ("chain17-c128-k13", spq.SPIN_C128, 17, workloads.chain(17), 0.1, 20, {}),
+    ("no-couplings", spq.SPIN_C64, 16, [], 0.1, 3, {}),
+    ("zero-steps", spq.SPIN_C64, 16, workloads.ladder(8), 0.1, 0, {}),
+    ("unfused", spq.SPIN_C64, 8, workloads.ladder(4), 0.1, 4, {"schedule": 1}),
+]
+
+
+@pytest.mark.parametrize("case", PROFILE_CASES, ids=[c[0] for c in PROFILE_CASES])
+def test_profile_plan_trace_observes_every_site_once(case):
+    """The all-site profile's plan: every (step, site) observable appears
+    exactly once, at a point of the op order where it equals the oracle's
+    profile, and the factors still realise the Strang product."""
+    name, prec, M, J, dt, steps, opts = case
+    o = spq.Options(**opts)
+    trace = spq.spin_plan_trace(prec, M, J, dt, steps, spq.SPIN_ALL_SITES, o)
+    info = spq.spin_describe_plan(prec, M, J, dt, steps, spq.SPIN_ALL_SITES, o)
+    assert int((trace[:, 0] == 0).sum()) == info["factor_ops"]
+    psi0 = oracle.random_phase_state(M, 0, 3)
+    Pw, _, psiw = oracle.trotter_profile(psi0, M, J, dt, steps)
+    psi = psi0.copy()
+    seen = {}
+    for kind, a, b, A, B in trace:
+        if kind == 1:
+            key = (int(a), int(b))
+            assert key not in seen, key
+            seen[key] = oracle.local_polarization(psi, M, int(b))
+        else:
+            oracle.apply_factor(psi, M, int(a), int(b), A, B, 1.0)
+    assert sorted(seen) == [(k, s) for k in range(steps + 1) for s in range(M)]
+    got = np.array([[seen[(k, s)] for s in range(M)] for k in range(steps + 1)])
+    assert np.abs(got - Pw).max() < 1e-11
+    assert np.abs(psi - psiw).max() < 1e-11
+
+
+def test_profile_plan_of_long_ladder_stays_fused():
+    J = workloads.ladder(15)
+    info = spq.spin_describe_plan(spq.SPIN_C64, 30, J, 0.05, 200, spq.SPIN_ALL_SITES)
+    base = spq.spin_describe_plan(spq.SPIN_C64, 30, J, 0.05, 200, 0)
+    assert info["path"] == 2
+    # Observing every site between steps blocks only the merges across step
+    # boundaries: at most one factor per coupling and step more.
+    assert base["factor_ops"] < info["factor_ops"] <= base["factor_ops"] + 200 * len(J)
+    # 30 per-site observables per step, at most 16 per pass: >= 2 passes a
+    # step; the plan stays close to that.
+    assert info["passes_per_step"] < 2.5
+    with pytest.raises(spq.SpinError) as e:
+        spq.spin_describe_plan(spq.SPIN_C64, 18, workloads.ladder(9), 0.05, 10, spq.SPIN_ALL_SITES,
+                               spq.Options(engine=1))
+    assert e.value.code == spq.SPIN_EUNSUPPORTED
+
+
 def test_long_ladder_plan_is_periodic_and_fused():
     J = workloads.ladder(15)
     info = spq.spin_describe_plan(spq.SPIN_C64, 30, J, 0.05, 1000, 0)

@@ -343,3 +343,42 @@ def test_c_oracle_matches_numpy_oracle():
     Pc, Nc = cref.trotter_run(psic, M, J, 0.04, 12, 5)
     assert np.abs(P - Pc).max() < 1e-13 and np.abs(N - Nc).max() < 1e-13
     assert np.abs(psi - psic).max() < 1e-14
+
+
+# ---------------------------------------------------------- all-site profile
+def test_profile_conserves_total_polarisation_and_starts_localised():
+    """Every two-spin term commutes with the total I^z, so sum_s P_s(t) is a
+    constant; the random-phase state polarised at site n has P_n = 1 and
+    P_s = 0 elsewhere exactly (half of its equal-weight configurations have
+    site s up)."""
+    M, n = 9, 4
+    J = workloads.star(M, n, a_over_b=-2.0) + [(1, 7, 0.3, -0.8)]
+    psi0 = oracle.random_phase_state(M, n, 5)
+    Pall, N, psi = oracle.trotter_profile(psi0, M, J, 0.07, 25)
+    e = np.zeros(M)
+    e[n] = 1.0
+    assert np.abs(Pall[0] - e).max() < 1e-13
+    assert np.abs(Pall.sum(axis=1) - 1.0).max() < 1e-12
+    assert np.abs(N - 1.0).max() < 1e-12
+    assert np.abs(Pall[:, 2]).max() > 1e-3       # the polarisation spreads
+
+
+def test_profile_free_fermion_chain_every_site():
+    """Basis-state average of the profile on an XY ladder without rungs: the
+    leg holding site 0 is an XY chain, so P_s = |g_s0|^2 of the single-
+    particle Strang product at each of its sites, and the other leg stays at
+    zero.  A wrong site index, sign or transposed propagator fails here."""
+    L = 4
+    M = 2 * L
+    J = workloads.ladder(L, bx=1.0, by=0.0)
+    bonds = [(i, j, b) for (i, j, a, b) in J if i < L and j < L]
+    xs = np.arange(2 ** M)
+    up0 = xs[(xs & 1) == 0]
+    psi0 = np.zeros((2 ** M, len(up0)), dtype=np.complex128)
+    psi0[up0, np.arange(len(up0))] = 1.0
+    Pall, _, _ = oracle.trotter_profile(psi0, M, J, 0.1, 60)
+    ens = Pall.mean(axis=2)
+    ff = ed.free_fermion_profile(L, bonds, 0.1, 60)
+    assert np.abs(ens[:, :L] - ff).max() < 1e-12
+    assert np.abs(ens[:, L:]).max() < 1e-12
+    assert ff[:, L - 1].max() > 0.1
