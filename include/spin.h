@@ -92,6 +92,20 @@ int spin_init_random_phase(void *psi, int32_t prec, int32_t M, int32_t polarized
                            uint64_t seed, void *stream);
 
 /*
+ * spin_init_product -- writes the product (unentangled) initial state of the
+ * section "Testing the quantum parallelism": site `polarized_site` up and
+ * every other site l in (|down> + exp(-i phi_l)|up>)/sqrt(2), i.e.
+ *   psi[x] = exp(-i sum_{l != n, bit l of x = 0} phi_l) / sqrt(2^(M-1))
+ *            if bit n of x is 0, else 0,
+ * with only M-1 independent phases phi_l = 2 pi u(seed, l) (u as above, at
+ * counter l).  Averages over N_alpha such draws approach the ensemble only
+ * for N_alpha (M-1) ~ 2^(M-1) (Fig. 3(a) discussion).
+ * Arguments, layout and errors as spin_init_random_phase.
+ */
+int spin_init_product(void *psi, int32_t prec, int32_t M, int32_t polarized_site,
+                      uint64_t seed, void *stream);
+
+/*
  * spin_trotter_evolve -- n_steps symmetric Trotter steps in place, with the
  * observable after every step.  Trotter-Suzuki route of the introduction and
  * summary (wave functions of size 2^M); observable of Eq. (2) with
@@ -178,9 +192,10 @@ typedef struct {
     void *psi;               /* device state of this problem, 2^M amplitudes */
     int32_t M, K;            /* size and number of couplings */
     int64_t coupling_offset; /* index of its first coupling in J_all */
-    int32_t polarized_site;  /* used with SPIN_INIT_RANDOM_PHASE */
+    int32_t polarized_site;  /* used with SPIN_INIT_RANDOM_PHASE and SPIN_INIT_PRODUCT */
     int32_t observed_site;
-    uint64_t seed;           /* phase seed (SPIN_INIT_RANDOM_PHASE) or basis index (SPIN_INIT_BASIS) */
+    uint64_t seed;           /* phase seed (SPIN_INIT_RANDOM_PHASE, SPIN_INIT_PRODUCT) or basis
+                                index (SPIN_INIT_BASIS) */
     double *P_dev;           /* n_steps+1 FP64 entries (required) */
     double *N_dev;           /* n_steps+1 FP64 entries or NULL */
 } spin_problem;
@@ -189,8 +204,9 @@ typedef struct {
 enum {
     SPIN_INIT_NONE = 0,          /* evolve the states as given */
     SPIN_INIT_RANDOM_PHASE = 1,  /* as spin_init_random_phase(polarized_site, seed) */
-    SPIN_INIT_BASIS = 2          /* the basis state |seed> (0 <= seed < 2^M): one member
+    SPIN_INIT_BASIS = 2,         /* the basis state |seed> (0 <= seed < 2^M): one member
                                     |Psi_i> of the ensemble of Eq. (1) */
+    SPIN_INIT_PRODUCT = 3        /* as spin_init_product(polarized_site, seed) */
 };
 
 /*

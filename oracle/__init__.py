@@ -25,7 +25,8 @@ Conventions (readings of the paper, fixed for parity):
 Parity status of every function is listed in its module header.
 """
 from .phase import splitmix64_next, phase_u, phase_u_array  # noqa: F401
-from .state import random_phase_state, random_phase_amplitudes, product_state  # noqa: F401
+from .state import (random_phase_state, random_phase_amplitudes, product_state,  # noqa: F401
+                    product_phases)
 from .trotter import (apply_factor, strang_factors, trotter_step,  # noqa: F401
                       trotter_run, trotter_profile, local_polarization, norm2)
 from . import ed, sector  # noqa: F401

@@ -54,6 +54,12 @@ def phase_pattern_state(M: int, n: int, phases: np.ndarray) -> np.ndarray:
     return np.where(up, amp, 0.0 + 0.0j)
 
 
+def product_phases(M: int, seed: int) -> np.ndarray:
+    """phi_l = 2 pi u(seed, l) for l = 0..M-1: the product state's M-1 random
+    phases drawn from the counter generator (the polarised site's is unused)."""
+    return 2.0 * np.pi * phase_u_array(seed, np.arange(M, dtype=np.uint64))
+
+
 def product_state(M: int, n: int, phis) -> np.ndarray:
     """Site n up, site l != n in (|down> + exp(-i phi_l)|up>)/sqrt(2).
 

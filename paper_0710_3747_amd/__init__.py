@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "SPIN_C64", "SPIN_C128", "SpinError", "library_path", "load_library",
-    "spin_init_random_phase", "spin_trotter_evolve", "spin_trotter_evolve_ex",
+    "spin_init_random_phase", "spin_init_product", "spin_trotter_evolve", "spin_trotter_evolve_ex",
     "spin_trotter_evolve_profile", "SPIN_ALL_SITES",
     "spin_local_polarization", "spin_trotter_evolve_batch", "spin_describe_plan",
     "spin_plan_trace", "spin_last_error", "spin_release_caches", "spin_version",
@@ -27,7 +27,7 @@ __all__ = [
 
 SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EHIP, SPIN_EUNSUPPORTED, SPIN_ENOTFOUND = 0, -1, -2, -3, -4, -5
 SPIN_C64, SPIN_C128 = 1, 2
-SPIN_INIT_NONE, SPIN_INIT_RANDOM_PHASE, SPIN_INIT_BASIS = 0, 1, 2
+SPIN_INIT_NONE, SPIN_INIT_RANDOM_PHASE, SPIN_INIT_BASIS, SPIN_INIT_PRODUCT = 0, 1, 2, 3
 SPIN_ALL_SITES = -1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -97,6 +97,7 @@ def load_library():
     cp = ctypes.POINTER(_Coupling)
     op = ctypes.POINTER(Options)
     lib.spin_init_random_phase.argtypes = [vp, i32, i32, i32, u64, vp]
+    lib.spin_init_product.argtypes = [vp, i32, i32, i32, u64, vp]
     lib.spin_trotter_evolve.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, vp]
     lib.spin_trotter_evolve_ex.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, op, vp]
     lib.spin_trotter_evolve_profile.argtypes = [vp, i32, i32, cp, i32, dbl, i64, vp, vp, op, vp]
@@ -115,7 +116,8 @@ def load_library():
     lib.spin_last_error.restype = ctypes.c_char_p
     lib.spin_version.restype = ctypes.c_char_p
     lib.spin_release_caches.restype = None
-    for name in ("spin_init_random_phase", "spin_trotter_evolve", "spin_trotter_evolve_ex",
+    for name in ("spin_init_random_phase", "spin_init_product", "spin_trotter_evolve",
+                 "spin_trotter_evolve_ex",
                  "spin_trotter_evolve_profile",
                  "spin_local_polarization", "spin_trotter_evolve_batch", "spin_prepare_plan",
                  "spin_describe_plan", "spin_plan_trace", "spin_autotune", "spin_tuned_options"):
@@ -188,6 +190,13 @@ def spin_init_random_phase(psi, M: int, polarized_site: int, seed: int, stream=N
     p, prec = _state(psi, M)
     _check(lib.spin_init_random_phase(p, prec, M, polarized_site, seed & (2 ** 64 - 1),
                                       _stream(stream)))
+
+
+def spin_init_product(psi, M: int, polarized_site: int, seed: int, stream=None) -> None:
+    """Writes the product state of M-1 random phases into ``psi`` (see include/spin.h)."""
+    lib = load_library()
+    p, prec = _state(psi, M)
+    _check(lib.spin_init_product(p, prec, M, polarized_site, seed & (2 ** 64 - 1), _stream(stream)))
 
 
 def spin_trotter_evolve_ex(psi, M: int, couplings, dt: float, n_steps: int, observed_site: int,

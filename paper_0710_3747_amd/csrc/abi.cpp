@@ -496,6 +496,19 @@ int spin_init_random_phase(void* psi, int32_t prec, int32_t M, int32_t polarized
     return SPIN_OK;
 }
 
+int spin_init_product(void* psi, int32_t prec, int32_t M, int32_t polarized_site, uint64_t seed,
+                      void* stream) {
+    int rc = validate_common(psi, prec, M);
+    if (rc) return rc;
+    if (polarized_site < 0 || polarized_site >= M) return fail(SPIN_EINVAL, "polarized_site out of range");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = prec == SPIN_C64 ? launch_init_product<float>(psi, M, polarized_site, seed, st)
+                                    : launch_init_product<double>(psi, M, polarized_site, seed, st);
+    if (e != hipSuccess) return fail(SPIN_EHIP, std::string("init launch: ") + hipGetErrorString(e));
+    g_err.clear();
+    return SPIN_OK;
+}
+
 int spin_local_polarization(const void* psi, int32_t prec, int32_t M, int32_t site,
                             double* out_dev, void* stream) {
     int rc = validate_common(psi, prec, M);

@@ -408,7 +408,7 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
                                          int32_t prec, double dt, int64_t n_steps,
                                          int32_t init, void* stream) {
     try {
-        if (init < SPIN_INIT_NONE || init > SPIN_INIT_BASIS) return fail(SPIN_EINVAL, "bad init");
+        if (init < SPIN_INIT_NONE || init > SPIN_INIT_PRODUCT) return fail(SPIN_EINVAL, "bad init");
         if (n < 0) return fail(SPIN_EINVAL, "n < 0");
         if (n > 0 && !probs) return fail(SPIN_EINVAL, "probs is NULL");
         if (K_total < 0 || (K_total > 0 && !J_all)) return fail(SPIN_EINVAL, "bad J_all / K_total");
@@ -426,7 +426,8 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
             if (!pr.P_dev) return fail(SPIN_EINVAL, os.str() + "P_dev is NULL");
             if (pr.observed_site < 0 || pr.observed_site >= pr.M)
                 return fail(SPIN_EINVAL, os.str() + "observed_site out of range");
-            if (init == SPIN_INIT_RANDOM_PHASE && (pr.polarized_site < 0 || pr.polarized_site >= pr.M))
+            if ((init == SPIN_INIT_RANDOM_PHASE || init == SPIN_INIT_PRODUCT) &&
+                (pr.polarized_site < 0 || pr.polarized_site >= pr.M))
                 return fail(SPIN_EINVAL, os.str() + "polarized_site out of range");
             if (init == SPIN_INIT_BASIS && (pr.seed >> pr.M) != 0)
                 return fail(SPIN_EINVAL, os.str() + "basis index (seed) >= 2^M");

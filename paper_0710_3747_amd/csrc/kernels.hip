@@ -1,6 +1,7 @@
 // kernels.hip -- gfx950 kernels of the random-phase Trotter path.
 //
 //  k_init        random-phase state (counter-based SplitMix64 phases)
+//  k_init_product  product state of M-1 random single-spin phases
 //  k_pass        one tiled sweep: a 2^k-amplitude tile per workgroup is
 //                staged through LDS; register stages apply the two-spin
 //                factors as three-shear rotations; observables are
@@ -36,6 +37,13 @@ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// u(seed, r) = (z >> 11) 2^-53 with z output r+1 of the SplitMix64 stream
+// started at `seed`, read directly at that counter.
+__device__ __forceinline__ double sm64_uniform(uint64_t seed, uint64_t r) {
+    const uint64_t z = sm64_mix(seed + (r + 1ull) * 0x9E3779B97F4A7C15ull);
+    return double(z >> 11) * 0x1.0p-53;
+}
+
 // Amplitude of basis state x of the random-phase state, FP64.
 __device__ __forceinline__ void random_phase_amp(uint64_t x, int n, uint64_t seed, double scale,
                                                  double* re, double* im) {
@@ -45,21 +53,44 @@ __device__ __forceinline__ void random_phase_amp(uint64_t x, int n, uint64_t see
         return;
     }
     const uint64_t r = (x & ((1ull << n) - 1ull)) | ((x >> (n + 1)) << n);
-    const uint64_t z = sm64_mix(seed + (r + 1ull) * 0x9E3779B97F4A7C15ull);
-    const double u = double(z >> 11) * 0x1.0p-53;
     double s, c;
-    sincospi(2.0 * u, &s, &c);      // phi = 2 pi u
+    sincospi(2.0 * sm64_uniform(seed, r), &s, &c);      // phi = 2 pi u
+    *re = c * scale;
+    *im = s * scale;
+}
+
+// Amplitude of basis state x of the product state: site n up, every other
+// site l in (|down> + exp(-i phi_l)|up>)/sqrt(2) with phi_l = 2 pi u(seed, l),
+// so psi[x] = 2^-(M-1)/2 exp(-i 2 pi sum of u(seed, l) over the up sites l != n).
+// `u` holds u(seed, l) for l < M (or is null: drawn here).
+__device__ __forceinline__ void product_amp(uint64_t x, int M, int n, uint64_t seed,
+                                            const double* u, double scale, double* re,
+                                            double* im) {
+    if ((x >> n) & 1ull) {
+        *re = 0.0;
+        *im = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int l = 0; l < M; ++l)
+        if (l != n && !((x >> l) & 1ull)) acc += u ? u[l] : sm64_uniform(seed, uint64_t(l));
+    acc -= floor(acc);               // the phase modulo 2 pi
+    double s, c;
+    sincospi(-2.0 * acc, &s, &c);
     *re = c * scale;
     *im = s * scale;
 }
 
 // Initial amplitude of basis state x: init 1 = the random-phase state,
-// init 2 = the basis state |seed> (one ensemble member of Eq. (1)).
-__device__ __forceinline__ void init_amp(uint64_t x, int init, int polarized, uint64_t seed,
+// init 2 = the basis state |seed> (one ensemble member of Eq. (1)), init 3 =
+// the product state of the random phases of `seed`.
+__device__ __forceinline__ void init_amp(uint64_t x, int M, int init, int polarized, uint64_t seed,
                                          double scale, double* re, double* im) {
     if (init == 2) {
         *re = x == seed ? 1.0 : 0.0;
         *im = 0.0;
+    } else if (init == 3) {
+        product_amp(x, M, polarized, seed, nullptr, scale, re, im);
     } else {
         random_phase_amp(x, polarized, seed, scale, re, im);
     }
@@ -73,6 +104,24 @@ __global__ __launch_bounds__(256) void k_init(typename CT<T>::c* __restrict__ ps
     for (uint64_t x = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < dim; x += stride) {
         double re, im;
         random_phase_amp(x, n, seed, scale, &re, &im);
+        typename CT<T>::c v;
+        v.x = T(re);
+        v.y = T(im);
+        psi[x] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_product(typename CT<T>::c* __restrict__ psi, int M,
+                                                      int n, uint64_t seed, double scale) {
+    __shared__ double u[64];
+    if (threadIdx.x < 64) u[threadIdx.x] = sm64_uniform(seed, threadIdx.x);
+    __syncthreads();
+    const uint64_t dim = 1ull << M;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t x = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < dim; x += stride) {
+        double re, im;
+        product_amp(x, M, n, seed, u, scale, &re, &im);
         typename CT<T>::c v;
         v.x = T(re);
         v.y = T(im);
@@ -689,7 +738,7 @@ __device__ __forceinline__ void resident_run(const ResidentJob& J, const DevStag
         const double scale = 1.0 / sqrt(ldexp(1.0, M - 1));
         for (uint32_t x = tid; x < dim; x += NT) {
             double re, im;
-            init_amp(x, J.init, J.polarized, J.seed, scale, &re, &im);
+            init_amp(x, M, J.init, J.polarized, J.seed, scale, &re, &im);
             C c;
             c.x = T(re);
             c.y = T(im);
@@ -851,7 +900,7 @@ __global__ __launch_bounds__(NT) void k_batch(const BatchProblem* __restrict__ p
             const double scale = 1.0 / sqrt(ldexp(1.0, B.M - 1));
             for (uint64_t x = uint64_t(rank) * NT + tid; x < dim; x += uint64_t(G) * NT) {
                 double re, im;
-                init_amp(x, B.init, B.polarized, B.seed, scale, &re, &im);
+                init_amp(x, B.M, B.init, B.polarized, B.seed, scale, &re, &im);
                 C c;
                 c.x = T(re);
                 c.y = T(im);
@@ -919,6 +968,15 @@ hipError_t launch_init(void* psi, int M, int n, uint64_t seed, hipStream_t st) {
     const double scale = 1.0 / sqrt(ldexp(1.0, M - 1));
     const int grid = grid_for(1ull << M, 256, 1 << 16);
     hipLaunchKernelGGL(k_init<T>, dim3(grid), dim3(256), 0, st,
+                       reinterpret_cast<typename CT<T>::c*>(psi), M, n, seed, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_product(void* psi, int M, int n, uint64_t seed, hipStream_t st) {
+    const double scale = 1.0 / sqrt(ldexp(1.0, M - 1));
+    const int grid = grid_for(1ull << M, 256, 1 << 16);
+    hipLaunchKernelGGL(k_init_product<T>, dim3(grid), dim3(256), 0, st,
                        reinterpret_cast<typename CT<T>::c*>(psi), M, n, seed, scale);
     return hipGetLastError();
 }
@@ -1076,6 +1134,8 @@ template hipError_t launch_batch<double>(int, const BatchProblem*, const BatchJo
                                          hipStream_t);
 template hipError_t launch_init<float>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_init<double>(void*, int, int, uint64_t, hipStream_t);
+template hipError_t launch_init_product<float>(void*, int, int, uint64_t, hipStream_t);
+template hipError_t launch_init_product<double>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_observe<float>(const void*, int, int, double*, int, hipStream_t);
 template hipError_t launch_observe<double>(const void*, int, int, double*, int, hipStream_t);
 template hipError_t launch_factor<float>(void*, int, int, int, double, double, double, double, int,

@@ -53,6 +53,8 @@ bool pass_shape_exists(bool f32, int r, int nt, int engine);
 template <typename T>
 hipError_t launch_init(void* psi, int M, int n, uint64_t seed, hipStream_t st);
 template <typename T>
+hipError_t launch_init_product(void* psi, int M, int n, uint64_t seed, hipStream_t st);
+template <typename T>
 hipError_t launch_observe(const void* psi, int M, int site, double* partials, int nblk,
                           hipStream_t st);
 hipError_t launch_reduce(const double* partials, int nwg, int ch, int64_t s0, int64_t count,

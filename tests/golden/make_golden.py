@@ -5,6 +5,13 @@
 phase_vectors.txt: (seed, r) -> SplitMix64 counter output z and
 u = (z >> 11) 2^-53 of the phase reading (phi_r = 2 pi u), for a fixed set
 of (seed, r) pairs including large counters and seeds near 2^64.
+
+ensemble_ladder2x7_by0p1.txt: the exact infinite-temperature ensemble
+polarisation P^ens_11(t) of Eq. (1) (exact diagonalisation, oracle.ed) for
+the 14-spin ladder of Fig. 3(a): XY couplings, b_x = 1 on the legs, b_y =
+b_x/10 on the rungs, site 0 polarised and observed, t = 0.05 k, k = 0..300.
+About three minutes of CPU; ``python tests/golden/make_golden.py phase``
+rewrites only the phase vectors.
 """
 import os
 import sys
@@ -13,6 +20,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.phase import GAMMA, MASK, _mix, phase_u  # noqa: E402
+import workloads  # noqa: E402
+
+
+def write_fig3a_ensemble():
+    import numpy as np
+    from oracle import ed
+    J = workloads.ladder(7, bx=1.0, by=0.1)
+    times = 0.05 * np.arange(301)
+    P = ed.ensemble_P_exact(14, J, times, 0, 0)
+    lines = ["# t P_ens  (Fig. 3(a) ladder 2x7, b_y/b_x = 1/10, XY, exact ensemble of Eq. (1))"]
+    lines += [f"{float(t):.17g} {float(p):.17g}" for t, p in zip(times, P)]
+    with open(os.path.join(HERE, "ensemble_ladder2x7_by0p1.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():
@@ -29,3 +49,5 @@ def main():
 
 if __name__ == "__main__":
     main()
+    if sys.argv[1:] != ["phase"]:
+        write_fig3a_ensemble()

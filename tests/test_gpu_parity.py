@@ -12,7 +12,7 @@ import oracle
 import workloads
 from oracle import cref, ed
 import paper_0710_3747_amd as spq
-from gpu_helpers import TOL_P, assert_state_close, gpu_evolve, gpu_state, note
+from gpu_helpers import TOL_P, assert_state_close, gpu_evolve, gpu_state, note, torch_dtype
 
 pytestmark = pytest.mark.gpu
 C64, C128 = spq.SPIN_C64, spq.SPIN_C128
@@ -439,3 +439,92 @@ def test_profile_rejects_matrix_engine_and_null_output():
     rc = lib.spin_trotter_evolve_profile(psi.data_ptr(), C64, 16, arr, K, 0.1, 2, None, None,
                                          None, None)
     assert rc == spq.SPIN_EINVAL and "Pall" in spq.spin_last_error()
+
+
+# ------------------------------------------------------------ product state
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,n,seed", [(1, 0, 3), (5, 2, 0), (14, 0, 77), (21, 20, 2 ** 64 - 5)])
+def test_init_product_matches_oracle(prec, M, n, seed):
+    """The product state of the section "Testing the quantum parallelism"
+    (site n up, M-1 single-spin phases), element by element."""
+    import torch
+    note("init product", prec, M, n, seed)
+    psi = torch.empty(2 ** M, dtype=torch_dtype(prec), device="cuda")
+    spq.spin_init_product(psi, M, n, seed)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().astype(np.complex128)
+    want = oracle.product_state(M, n, oracle.product_phases(M, seed))
+    # The GPU sums up to M-1 phases before one sincos; the oracle multiplies
+    # M-1 complex factors: both round at ~M ulps of the phase sum (< M).
+    tol = 4e-15 * M if prec == C128 else 2e-7
+    assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_product_init_matches_single_runs(prec):
+    """SPIN_INIT_PRODUCT inside the batched launch (states held in LDS and a
+    gang) equals spin_init_product followed by spin_trotter_evolve."""
+    import torch
+    note("batch product init", prec)
+    steps, dt = 20, 0.03
+    probs, singles = [], []
+    for idx, (M, seed) in enumerate([(10, 4), (12, 9), (16, 2), (18, 31)]):
+        J = workloads.star(M, 40 + idx)
+        pol = idx % M
+        psi = torch.zeros(2 ** M, dtype=torch_dtype(prec), device="cuda")
+        P = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+        probs.append(dict(psi=psi, M=M, couplings=J, observed_site=0, P=P, polarized_site=pol,
+                          seed=seed))
+        ref = torch.empty_like(psi)
+        spq.spin_init_product(ref, M, pol, seed)
+        Pr = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+        spq.spin_trotter_evolve(ref, M, J, dt, steps, 0, Pr)
+        singles.append((ref, Pr))
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init=spq.SPIN_INIT_PRODUCT)
+    torch.cuda.synchronize()
+    for pr, (ref, Pr) in zip(probs, singles):
+        assert np.abs(pr["P"].cpu().numpy() - Pr.cpu().numpy()).max() < 2e-5
+        assert_state_close(pr["psi"].cpu().numpy().astype(np.complex128),
+                           ref.cpu().numpy().astype(np.complex128), prec)
+
+
+def test_fig3a_entangled_vs_product_states_M14():
+    """Fig. 3(a), qualitatively, on the 14-spin ladder with b_y/b_x = 1/10:
+    one random entangled state follows the exact ensemble (stored, from the
+    oracle's exact diagonalisation) within the O(2^-(M-1)/2) deviation; one
+    product state (M-1 phases) does not; the mean of N_alpha = 630 product
+    states, run as one batched launch, does (630 (M-1) ~ 2^(M-1))."""
+    import os
+    import torch
+    M, dt, steps = 14, 0.05, 300
+    J = workloads.ladder(7, bx=1.0, by=0.1)
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "ensemble_ladder2x7_by0p1.txt"))
+    assert np.allclose(gold[:, 0], dt * np.arange(steps + 1))
+    Pens = gold[:, 1]
+    sigma = 2.0 ** (-(M - 1) / 2)
+    rms = lambda P: float(np.sqrt(np.mean((P - Pens) ** 2)))
+    note("fig3a singles")
+    ent, prod = [], []
+    for seed in range(4):
+        Pe, _, _, _ = gpu_evolve(C128, M, J, dt, steps, 0, seed=seed, keep_state=False)
+        psi = torch.empty(2 ** M, dtype=torch.complex128, device="cuda")
+        spq.spin_init_product(psi, M, 0, seed)
+        Pp, _, _, _ = gpu_evolve(C128, M, J, dt, steps, 0, psi=psi, keep_state=False)
+        ent.append(rms(Pe))
+        prod.append(rms(Pp))
+    note("fig3a rms ent", ent, "prod", prod, "sigma", sigma)
+    assert max(ent) < 2 * sigma
+    assert all(p > 2 * e for p, e in zip(prod, ent))
+    assert np.median(prod) > 3 * sigma
+    note("fig3a batch of 630 product states")
+    probs = []
+    for a in range(630):
+        probs.append(dict(psi=torch.zeros(2 ** M, dtype=torch.complex64, device="cuda"), M=M,
+                          couplings=J, observed_site=0, polarized_site=0, seed=1000 + a,
+                          P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
+    spq.spin_trotter_evolve_batch(probs, C64, dt, steps, init=spq.SPIN_INIT_PRODUCT)
+    torch.cuda.synchronize()
+    mean = np.mean([p["P"].cpu().numpy() for p in probs], axis=0)
+    note("fig3a rms mean630", rms(mean))
+    assert rms(mean) < 2 * sigma
+    assert rms(mean) < np.median(prod) / 3

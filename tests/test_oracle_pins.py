@@ -382,3 +382,20 @@ def test_profile_free_fermion_chain_every_site():
     assert np.abs(ens[:, :L] - ff).max() < 1e-12
     assert np.abs(ens[:, L:]).max() < 1e-12
     assert ff[:, L - 1].max() > 0.1
+
+
+def test_product_phases_are_the_counter_generator_outputs():
+    """phi_l = 2 pi u(seed, l): the stored published-definition outputs of
+    the generator fix the product state's phases."""
+    import os
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden", "phase_vectors.txt"))
+            if not l.startswith("#")]
+    for s, r, _, u in rows:
+        if int(r) < 8:
+            ph = oracle.product_phases(8, int(s))
+            assert ph[int(r)] == 2.0 * np.pi * float(u)
+    M, n = 6, 2
+    ph = oracle.product_phases(M, 12)
+    psi = oracle.product_state(M, n, ph)
+    x = 0b101001   # sites 0, 3, 5 down; up sites other than n: 1, 4
+    assert abs(psi[x] - np.exp(-1j * (ph[1] + ph[4])) / np.sqrt(2.0 ** (M - 1))) < 1e-15
