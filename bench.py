@@ -74,6 +74,30 @@ def run_path(spq, torch, w, prec, steps, warmup, opts=None):
     return out
 
 
+def run_profile(spq, torch, w, steps, opts=None):
+    """All-site profile (every site's P after every step) on the complex64
+    state: plan prepared outside the timed region, then one timed call."""
+    M, J, dt = w["M"], w["J"], w["dt"]
+    psi = torch.empty(2 ** M, dtype=torch.complex64, device="cuda")
+    Pall = torch.empty((steps + 1) * M, dtype=torch.float64, device="cuda")
+    N = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+    spq.spin_init_random_phase(psi, M, w["polarized"], w["seed"])
+    spq.spin_prepare_plan(spq.SPIN_C64, M, J, dt, steps, spq.SPIN_ALL_SITES, opts)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    spq.spin_trotter_evolve_profile(psi, M, J, dt, steps, Pall, N, opts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    info = spq.spin_describe_plan(spq.SPIN_C64, M, J, dt, steps, spq.SPIN_ALL_SITES, opts)
+    P = Pall.cpu().numpy().reshape(steps + 1, M)
+    out = dict(ms_total=e0.elapsed_time(e1), P=P, N=N.cpu().numpy(), info=info)
+    del psi
+    torch.cuda.empty_cache()
+    return out
+
+
 def summarize(res, w, steps, prec_bytes):
     M, K = w["M"], len(w["J"])
     amp_updates = 2 * K * 2 ** M * steps
@@ -254,6 +278,8 @@ def main():
                     help="use the default launch shape instead of the autotuner's choice")
     ap.add_argument("--engine-steps", type=int, default=100,
                     help="steps of the MFMA-matrix vs VALU-butterfly comparison (0 = skip)")
+    ap.add_argument("--profile-steps", type=int, default=100,
+                    help="steps of the all-site profile leg (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -297,7 +323,8 @@ def main():
         tuned["c64" if prec == spq.SPIN_C64 else "c128"] = {
             "seconds": time.perf_counter() - t0, "trial_steps": 16,
             "candidates": [{k: r[k] for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine",
-                                               "ms_per_step", "passes_per_step")} for r in out["results"]],
+                                               "ms_per_step", "trial_ms_per_step", "passes_per_step")}
+                           for r in out["results"]],
             "chosen": {k: getattr(out["best"], k) for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine")}}
         return out["best"]
 
@@ -374,6 +401,24 @@ def main():
         if res64 is not None:
             cmp["max_dP_mfma_vs_fp64"] = float(np.abs(rm["P"] - res64["P"][: n + 1]).max())
         out["engine_comparison"] = cmp
+    if args.workload == "ladder_2x15" and res32 is not None and args.profile_steps > 0:
+        # every site's polarisation after every step, in the same passes
+        import numpy as np
+        n = min(args.profile_steps, steps)
+        # the shape the headline ran with (explicit, autotuned, or default)
+        o = opts if (opts is not None or args.no_autotune) else spq.spin_tuned_options(
+            spq.SPIN_C64, w["M"], w["J"], w["dt"], w["observed"])
+        print(f"[bench] all-site profile, {n} steps", file=sys.stderr, flush=True)
+        rp = run_profile(spq, torch, w, n, o)
+        rs = run_path(spq, torch, w, spq.SPIN_C64, n, 2, o)
+        out["all_site_profile"] = {
+            "steps": n, "sites": w["M"],
+            "ms_per_step": rp["ms_total"] / n,
+            "single_site_ms_per_step": rs["ms_total"] / n,
+            "time_ratio": rp["ms_total"] / rs["ms_total"],
+            "passes_per_step": rp["info"]["passes_per_step"],
+            "max_dP_site0_vs_single_site": float(np.abs(rp["P"][:, w["observed"]] - rs["P"]).max()),
+            "max_total_polarisation_drift": float(np.abs(rp["P"].sum(axis=1) - rp["P"][0].sum()).max())}
     if args.workload != "ladder_2x15":
         out["metric"] = "amplitude-updates/s per Trotter step (secondary workload)"
     elif not args.no_batch:

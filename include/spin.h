@@ -253,6 +253,10 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  *   - cache_path: if not NULL, a JSON file that receives the choice (created,
  *     or updated keeping other entries; written atomically by rename).
  * States small enough for one workgroup have a single shape (one trial).
+ * A trial of a few steps runs on a short plan whose passes per step differ
+ * from a long run's (the plan repeats in blocks of tens of steps), so the
+ * ranking is the trial's time per pass launch times the passes per step of
+ * the candidate's plan for a 1000-step run (or trial_steps, if longer).
  * Planning is done before each timed trial and is not part of the times.
  * Errors as spin_trotter_evolve_ex; SPIN_ENOMEM if the scratch state cannot
  * be allocated; SPIN_EUNSUPPORTED if no candidate ran.
@@ -262,10 +266,13 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  * there is none.  Host only.
  */
 typedef struct {
-    spin_options opt;        /* the candidate */
-    double ms_per_step;      /* trial time per step, -1 if the candidate failed */
-    double passes_per_step;  /* of the trial's plan */
-    int32_t status;          /* spin_status of the candidate's trial */
+    spin_options opt;          /* the candidate */
+    double ms_per_step;        /* ranking: trial time per pass launch x passes_per_step
+                                  (the trial time per step for one-workgroup states);
+                                  -1 if the candidate failed */
+    double trial_ms_per_step;  /* measured time per step of the trial itself */
+    double passes_per_step;    /* of the plan of a 1000-step run (host planning) */
+    int32_t status;            /* spin_status of the candidate's trial */
     int32_t reserved_;
 } spin_tune_result;
 

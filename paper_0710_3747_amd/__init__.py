@@ -57,6 +57,7 @@ class Options(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     """``spin_tune_result``."""
     _fields_ = [("opt", Options), ("ms_per_step", ctypes.c_double),
+                ("trial_ms_per_step", ctypes.c_double),
                 ("passes_per_step", ctypes.c_double), ("status", ctypes.c_int32),
                 ("reserved_", ctypes.c_int32)]
 
@@ -302,7 +303,8 @@ def spin_autotune(prec: int, M: int, couplings, dt: float, observed_site: int,
     out = []
     for r in res[: min(n.value, 16)]:
         d = _opt_dict(r.opt)
-        d.update(ms_per_step=r.ms_per_step, passes_per_step=r.passes_per_step, status=r.status)
+        d.update(ms_per_step=r.ms_per_step, trial_ms_per_step=r.trial_ms_per_step,
+                 passes_per_step=r.passes_per_step, status=r.status)
         out.append(d)
     return {"best": best, "results": out}
 

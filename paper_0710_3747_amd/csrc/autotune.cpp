@@ -6,6 +6,7 @@
 // entry points on a scratch state.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cinttypes>
 #include <cmath>
 #include <cstdio>
@@ -27,6 +28,9 @@ struct Tuned {
     int tile_bits, reg_bits, coalesce_bits, engine;
     double ms_per_step;
 };
+
+// Length of the run whose plan scales the trial time per pass.
+constexpr int64_t kTuneLongSteps = 1000;
 
 std::mutex g_tune_mu;
 std::map<std::string, Tuned> g_tuned;
@@ -181,14 +185,21 @@ extern "C" int spin_autotune(int32_t prec, int32_t M, const spin_coupling* J, in
         if (hipEventCreate(&b.e0) != hipSuccess || hipEventCreate(&b.e1) != hipSuccess)
             return fail(SPIN_EHIP, "hipEventCreate failed");
 
+        // A short trial measures the time of one pass launch of each shape;
+        // the ranking scales it by the passes per step of a long run's plan
+        // (host planning only), whose repeating block a short trial's plan
+        // does not reach.
+        const int64_t long_steps = std::max<int64_t>(trial_steps, kTuneLongSteps);
         int nres = 0, ibest = -1;
         for (size_t ci = 0; ci < cand.size(); ++ci) {
             Tuned& t = cand[ci];
             spin_options o = to_options(t);
-            spin_plan_info info;
+            spin_plan_info info, linfo;
             std::memset(&info, 0, sizeof info);
+            std::memset(&linfo, 0, sizeof linfo);
             int crc = spin_prepare_plan(prec, M, J, K, dt, trial_steps, observed_site, &o);
             if (crc == SPIN_OK) crc = spin_describe_plan(prec, M, J, K, dt, trial_steps, observed_site, &o, &info);
+            if (crc == SPIN_OK) crc = spin_describe_plan(prec, M, J, K, dt, long_steps, observed_site, &o, &linfo);
             if (crc == SPIN_OK) crc = spin_init_random_phase(b.psi, prec, M, 0, 1, st);
             if (crc == SPIN_OK)   // warm-up
                 crc = spin_trotter_evolve_ex(b.psi, prec, M, J, K, dt, trial_steps, observed_site, b.P, b.N, &o, st);
@@ -200,14 +211,19 @@ extern "C" int spin_autotune(int32_t prec, int32_t M, const spin_coupling* J, in
                     hipEventElapsedTime(&ms, b.e0, b.e1) != hipSuccess)
                     return fail(SPIN_EHIP, "autotune timing failed");
             }
-            t.ms_per_step = crc == SPIN_OK ? double(ms) / double(trial_steps) : -1.0;
+            const double trial = crc == SPIN_OK ? double(ms) / double(trial_steps) : -1.0;
+            // one workgroup holds the state: one launch, nothing to scale
+            const bool tiled = crc == SPIN_OK && info.path == 2 && info.launches > 0;
+            t.ms_per_step = !tiled ? trial
+                                   : double(ms) / double(info.launches) * linfo.passes_per_step;
             if (crc == SPIN_OK && (ibest < 0 || t.ms_per_step < cand[ibest].ms_per_step)) ibest = int(ci);
             if (nres < cap) {
                 spin_tune_result& r = results[nres];
                 std::memset(&r, 0, sizeof r);
                 r.opt = o;
                 r.ms_per_step = t.ms_per_step;
-                r.passes_per_step = info.passes_per_step;
+                r.trial_ms_per_step = trial;
+                r.passes_per_step = tiled ? linfo.passes_per_step : info.passes_per_step;
                 r.status = crc;
             }
             ++nres;
