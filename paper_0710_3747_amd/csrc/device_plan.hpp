@@ -17,7 +17,7 @@ constexpr int kMaxRegBits = 6;      // at most 64 amplitudes per lane
 constexpr int kMaxMeas = 4;         // observable slots one pass can hold
 constexpr int kMaxSites = 40;
 constexpr int kBatchRing = 16;      // observable slots per gang problem (steps mod 16)
-constexpr int kMaxMeasProfile = 16; // per-site observables one pass can hold (all-site profile)
+constexpr int kMaxMeasProfile = 64; // per-site observables one pass can hold (all-site profile)
 
 // Op codes.  A two-spin factor on register bits (qa < qb) of a stage has
 // code qa*8 + qb; kOpZZ is or-ed in when the factor carries an I^z I^z

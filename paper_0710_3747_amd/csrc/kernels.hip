@@ -522,12 +522,26 @@ __device__ __forceinline__ int64_t lane_offset(const int64_t* gt, int tid) {
     return o;
 }
 
-// All-site profile accumulators of a lane: slot m of the pass's per-site
-// observables, and the norm slots.
-struct ProfAcc {
-    double p[kMaxMeasProfile];
-    double n[kMaxMeas];
-};
+// Wave sum of a double, valid in lane 63: DPP adds over pairs, quads,
+// half rows, rows, then rows 0+1 into row 1 and 2+3 into row 3
+// (row_bcast:15), then rows 0..1 into rows 2..3 (row_bcast:31).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, ROW_MASK, 0xF, false);
+    return v + __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+__device__ __forceinline__ double wave_sum_last(double v) {
+    v = dpp_add<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xF>(v);    // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);    // row_mirror
+    v = dpp_add<0x142, 0xA>(v);    // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xC>(v);    // row_bcast:31 into rows 2, 3
+    return v;
+}
 
 // One per-site observable (profile kOpMeas) of the lane's registers: the
 // sign of each amplitude follows the site's bit (thread bit, register bit or
@@ -553,7 +567,7 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                                            unsigned G, int64_t tiles_per_member, char* ldsb,
                                            double (&accP)[kMaxMeas], double (&accN)[kMaxMeas],
                                            const float* __restrict__ mats = nullptr,
-                                           ProfAcc* prof = nullptr) {
+                                           double* pacc = nullptr, double* nacc = nullptr) {
     using C = typename CT<T>::c;
     const int tid = threadIdx.x;
     const DevStage& S0 = stages[P.stage0];
@@ -604,15 +618,46 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                 }
                 if (o < o1) {    // observable of the state at this point
                     if constexpr (PROFILE) {
-                        double p, n;
-                        int slot, nslot;
-                        prof_observe<R>(v, ops[o].aux, base, p, n, slot, nslot);
+                        // Every per-site observable at this point from the
+                        // lane's total weight and its register-bit half sums,
+                        // each squared once; wave sums go to the wave's LDS
+                        // row (pacc / nacc), one row per wave.
+                        double tot = 0.0, half[R];
 #pragma unroll
-                        for (int m = 0; m < kMaxMeasProfile; ++m)
-                            if (m == slot) prof->p[m] += p;
+                        for (int b = 0; b < R; ++b) half[b] = 0.0;
 #pragma unroll
-                        for (int m = 0; m < kMaxMeas; ++m)
-                            if (m == nslot) prof->n[m] += n;
+                        for (int j = 0; j < (1 << R); ++j) {
+                            const double w = double(v[j].x) * double(v[j].x) + double(v[j].y) * double(v[j].y);
+                            tot += w;
+#pragma unroll
+                            for (int b = 0; b < R; ++b)
+                                if ((j >> b) & 1) half[b] += w;
+                        }
+                        const bool last = (tid & 63) == 63;
+                        while (o < o1 && ops[o].code == kOpMeas) {
+                            const int aux = ops[o].aux;
+                            const int slot = aux & 63, kind = (aux >> 6) & 3, idx = (aux >> 8) & 63;
+                            const int nslot = ((aux >> 14) & 7) - 1;
+                            double p;
+                            if (kind == 1) {
+                                double h = half[0];
+#pragma unroll
+                                for (int b = 1; b < R; ++b)
+                                    if (b == idx) h = half[b];
+                                p = tot - 2.0 * h;
+                            } else {
+                                const int neg = kind == 0 ? ((tid >> idx) & 1) : int((base >> idx) & 1);
+                                p = neg ? -tot : tot;
+                            }
+                            p = wave_sum_last(p);
+                            if (last) pacc[slot] += p;
+                            if (nslot >= 0) {
+                                const double n = wave_sum_last(tot);
+                                if (last) nacc[nslot] += n;
+                            }
+                            ++o;
+                        }
+                        continue;
                     } else {
                         const int slot = ops[o].aux;
                         double p = 0.0, n = 0.0;
@@ -678,29 +723,36 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
     const unsigned G = gridDim.x, w = blockIdx.x;
     const unsigned wperm = (G >= 8) ? (w % 8u) * (G / 8u) + w / 8u : w;
     if constexpr (PROFILE) {
-        ProfAcc prof;
-#pragma unroll
-        for (int m = 0; m < kMaxMeasProfile; ++m) prof.p[m] = 0.0;
-#pragma unroll
-        for (int m = 0; m < kMaxMeas; ++m) prof.n[m] = 0.0;
+        // Per-wave accumulator rows; lane 63 of each wave owns its row.
+        constexpr int NW = NT / 64;
+        __shared__ double pacc[NW][kMaxMeasProfile];
+        __shared__ double nacc[NW][kMaxMeas];
+        const int wave = threadIdx.x / 64;
+        if ((threadIdx.x & 63) == 63) {
+            for (int m = 0; m < kMaxMeasProfile; ++m) pacc[wave][m] = 0.0;
+            for (int m = 0; m < kMaxMeas; ++m) nacc[wave][m] = 0.0;
+        }
         pass_tiles<T, R, NT, WRITES, ENGINE, true>(psi, P, stages, ops, wperm, G, tiles_per_wg,
                                                    reinterpret_cast<char*>(lds), accP, accN, mats,
-                                                   &prof);
+                                                   pacc[wave], nacc[wave]);
+        __syncthreads();
         const int M = P.k + P.nfree;
         auto dst = [&](int64_t step) {
             return partials + ((size_t)((step_offset + step) % ch) * nwg + blockIdx.x) * (M + 1);
         };
-#pragma unroll
-        for (int m = 0; m < kMaxMeasProfile; ++m) {
-            if (m >= P.pmeas) break;
-            const double v = block_sum1<NT>(prof.p[m], red);
-            if (threadIdx.x == 0) dst(P.pmeas_step[m])[P.pmeas_site[m]] = v;
+        // fixed-order sums over the waves
+        for (int m = threadIdx.x; m < P.pmeas; m += NT) {
+            double v = 0.0;
+            for (int w = 0; w < NW; ++w) v += pacc[w][m];
+            dst(P.pmeas_step[m])[P.pmeas_site[m]] = v;
         }
-#pragma unroll
-        for (int m = 0; m < kMaxMeas; ++m) {
-            if (m >= P.pnorm) break;
-            const double v = block_sum1<NT>(prof.n[m], red);
-            if (threadIdx.x == 0) dst(P.pmeas_step[P.pnorm_meas[m]])[M] = v;
+        if (threadIdx.x >= NT - kMaxMeas) {
+            const int m = threadIdx.x - (NT - kMaxMeas);
+            if (m < P.pnorm) {
+                double v = 0.0;
+                for (int w = 0; w < NW; ++w) v += nacc[w][m];
+                dst(P.pmeas_step[P.pnorm_meas[m]])[M] = v;
+            }
         }
         return;
     }

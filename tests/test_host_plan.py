@@ -164,9 +164,9 @@ def test_profile_plan_of_long_ladder_stays_fused():
     # Observing every site between steps blocks only the merges across step
     # boundaries: at most one factor per coupling and step more.
     assert base["factor_ops"] < info["factor_ops"] <= base["factor_ops"] + 200 * len(J)
-    # 30 per-site observables per step, at most 16 per pass: >= 2 passes a
-    # step; the plan stays close to that.
-    assert info["passes_per_step"] < 2.5
+    # 30 per-site observables per step ride in the passes that hold their
+    # sites (up to 64 per pass): few passes beyond the one-site plan's.
+    assert info["passes_per_step"] < 1.25 * base["passes_per_step"]
     with pytest.raises(spq.SpinError) as e:
         spq.spin_describe_plan(spq.SPIN_C64, 18, workloads.ladder(9), 0.05, 10, spq.SPIN_ALL_SITES,
                                spq.Options(engine=1))
