@@ -137,7 +137,11 @@ typedef struct {
                              (complex64, tile_bits 14, reg_bits 5; tiled path only:
                              states held by one workgroup ignore it) */
     int32_t no_merge;     /* 1 = do not merge adjacent same-pair factors */
-    int32_t use_graph;    /* 1 = launch through a captured hipGraph */
+    int32_t use_graph;    /* 1 = tiled path: the call's launch sequence is captured
+                             into a hipGraph once per (plan, state, P, N, workspace)
+                             and replayed on a library stream ordered after `stream`
+                             (for calls that repeat); ignored by states held by one
+                             workgroup and by the unfused schedule */
     int32_t reserved[9];
 } spin_options;
 

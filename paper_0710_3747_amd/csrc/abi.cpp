@@ -305,6 +305,76 @@ int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t
     return SPIN_OK;
 }
 
+// ------------------------------------------------------------- graphs
+// The launch sequence of one tiled evolve call, captured once per plan and
+// set of buffers baked into the kernel arguments, and replayed on a library
+// stream that is ordered after the caller's stream and before its later
+// work (the call stays asynchronous).
+struct GraphKey {
+    const void* plan;
+    void* psi;
+    double* P;
+    double* N;
+    void* part;
+    int dev;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(plan, psi, P, N, part, dev) < std::tie(o.plan, o.psi, o.P, o.N, o.part, o.dev);
+    }
+};
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+static std::mutex g_graph_mu;
+static std::map<GraphKey, GraphEntry> g_graphs;
+static std::map<int, hipStream_t> g_graph_stream;
+
+template <typename F>
+static int run_as_graph(const GraphKey& key, F&& enqueue, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    hipStream_t& side = g_graph_stream[key.dev];
+    if (!side) HIP_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        HIP_TRY(hipStreamBeginCapture(side, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue(side);
+        GraphEntry ge;
+        const hipError_t e = hipStreamEndCapture(side, &ge.graph);
+        if (rc != SPIN_OK || e != hipSuccess) {
+            if (ge.graph) (void)hipGraphDestroy(ge.graph);
+            return rc != SPIN_OK ? rc : fail(SPIN_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        const hipError_t ei = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(ge.graph);
+            return fail(SPIN_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        }
+        it = g_graphs.emplace(key, ge).first;
+    }
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, ev, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(it->second.exec, side);
+    if (e == hipSuccess) e = hipEventRecord(ev, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return fail(SPIN_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    return SPIN_OK;
+}
+
+static void release_graphs() {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& kv : g_graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    g_graphs.clear();
+    for (auto& kv : g_graph_stream)
+        if (kv.second) (void)hipStreamDestroy(kv.second);
+    g_graph_stream.clear();
+}
+
 // ------------------------------------------------------------- evolve
 template <typename T>
 static int evolve_naive(void* psi, int M, const std::vector<Coupling>& J, double dt,
@@ -355,7 +425,7 @@ static int evolve_naive(void* psi, int M, const std::vector<Coupling>& J, double
 // complete steps are reduced in chunks out of a ring of `ch` step slots.
 template <typename T>
 static int evolve_profile(void* psi, int M, const DevicePlan& dp, int64_t n_steps, double* P,
-                          double* N, hipStream_t st) {
+                          double* N, bool graph, hipStream_t st) {
     if (dp.resident) {
         ResidentJob job{};
         job.psi = psi;
@@ -378,41 +448,49 @@ static int evolve_profile(void* psi, int M, const DevicePlan& dp, int64_t n_step
     int rc = scratch_get(st, size_t(ch) * dp.nwg * (M + 1) * sizeof(double), &scratch);
     if (rc) return rc;
     double* part = static_cast<double*>(scratch);
-    std::vector<int64_t> next(M, 0);    // per site: steps measured so far
-    int64_t complete = 0, reduced = 0, highest = 0;
-    const size_t nl = dp.sp.launch_tmpl.size();
-    for (size_t l = 0; l < nl; ++l) {
-        const int t = dp.sp.launch_tmpl[l];
-        const int64_t off = dp.sp.launch_offset[l];
-        for (int64_t s : dp.meas[t]) highest = std::max(highest, s + off + 1);
-        if (highest - reduced > ch) {
+    auto enqueue = [&](hipStream_t st) -> int {
+        std::vector<int64_t> next(M, 0);    // per site: steps measured so far
+        int64_t complete = 0, reduced = 0, highest = 0;
+        const size_t nl = dp.sp.launch_tmpl.size();
+        for (size_t l = 0; l < nl; ++l) {
+            const int t = dp.sp.launch_tmpl[l];
+            const int64_t off = dp.sp.launch_offset[l];
+            for (int64_t s : dp.meas[t]) highest = std::max(highest, s + off + 1);
+            if (highest - reduced > ch) {
+                std::ostringstream os;
+                os << "internal: profile measurements run " << highest - reduced
+                   << " steps ahead of the reduction (ring of " << ch << ")";
+                return fail(SPIN_EUNSUPPORTED, os.str());
+            }
+            PassShape shp = dp.shape;
+            shp.writes = dp.sp.passes[t].writes;
+            HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp.d_passes),
+                                    static_cast<const DevStage*>(dp.d_stages),
+                                    static_cast<const DevOp<T>*>(dp.d_ops), t, dp.tiles_per_wg,
+                                    dp.nwg, part, off, ch, st)));
+            for (size_t m = 0; m < dp.meas[t].size(); ++m) {
+                int64_t& nx = next[dp.meas_site[t][m]];
+                nx = std::max(nx, dp.meas[t][m] + off + 1);
+            }
+            complete = *std::min_element(next.begin(), next.end());
+            if (complete - reduced >= ch / 2 || (l + 1 == nl && complete > reduced)) {
+                HIP_TRY(launch_reduce_profile(part, dp.nwg, ch, M, reduced, complete - reduced, P, N, st));
+                reduced = complete;
+            }
+        }
+        if (reduced != total) {
             std::ostringstream os;
-            os << "internal: profile measurements run " << highest - reduced
-               << " steps ahead of the reduction (ring of " << ch << ")";
+            os << "internal: profile plan measured " << reduced << " of " << total << " steps";
             return fail(SPIN_EUNSUPPORTED, os.str());
         }
-        PassShape shp = dp.shape;
-        shp.writes = dp.sp.passes[t].writes;
-        HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp.d_passes),
-                                static_cast<const DevStage*>(dp.d_stages),
-                                static_cast<const DevOp<T>*>(dp.d_ops), t, dp.tiles_per_wg,
-                                dp.nwg, part, off, ch, st)));
-        for (size_t m = 0; m < dp.meas[t].size(); ++m) {
-            int64_t& nx = next[dp.meas_site[t][m]];
-            nx = std::max(nx, dp.meas[t][m] + off + 1);
-        }
-        complete = *std::min_element(next.begin(), next.end());
-        if (complete - reduced >= ch / 2 || (l + 1 == nl && complete > reduced)) {
-            HIP_TRY(launch_reduce_profile(part, dp.nwg, ch, M, reduced, complete - reduced, P, N, st));
-            reduced = complete;
-        }
+        return SPIN_OK;
+    };
+    if (graph) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        return run_as_graph(GraphKey{&dp, psi, P, N, part, dev}, enqueue, st);
     }
-    if (reduced != total) {
-        std::ostringstream os;
-        os << "internal: profile plan measured " << reduced << " of " << total << " steps";
-        return fail(SPIN_EUNSUPPORTED, os.str());
-    }
-    return SPIN_OK;
+    return enqueue(st);
 }
 
 template <typename T>
@@ -424,7 +502,8 @@ static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double
     int rc = get_plan(sizeof(T) == 4 ? SPIN_C64 : SPIN_C128, M, J, dt, n_steps, observed, opt,
                       profile, &dp, &sh);
     if (rc) return rc;
-    if (profile) return evolve_profile<T>(psi, M, *dp, n_steps, P, N, st);
+    const bool graph = opt && opt->use_graph;
+    if (profile) return evolve_profile<T>(psi, M, *dp, n_steps, P, N, graph, st);
     if (dp->resident) {
         ResidentJob job{};
         job.psi = psi;
@@ -447,30 +526,38 @@ static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double
     rc = scratch_get(st, size_t(ch) * dp->nwg * 2 * sizeof(double), &scratch);
     if (rc) return rc;
     double* part = static_cast<double*>(scratch);
-    int64_t measured = 0, reduced = 0;
-    const size_t nl = dp->sp.launch_tmpl.size();
-    for (size_t l = 0; l < nl; ++l) {
-        const int t = dp->sp.launch_tmpl[l];
-        const int64_t off = dp->sp.launch_offset[l];
-        PassShape shp = dp->shape;
-        shp.mats = static_cast<const float*>(dp->d_mats);
-        shp.writes = dp->sp.passes[t].writes;
-        HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp->d_passes),
-                                static_cast<const DevStage*>(dp->d_stages),
-                                static_cast<const DevOp<T>*>(dp->d_ops), t, dp->tiles_per_wg,
-                                dp->nwg, part, off, ch, st)));
-        for (int64_t s : dp->meas[t]) measured = std::max(measured, s + off + 1);
-        if (measured - reduced >= ch / 2 || (l + 1 == nl && measured > reduced)) {
-            HIP_TRY(launch_reduce(part, dp->nwg, ch, reduced, measured - reduced, P, N, st));
-            reduced = measured;
+    auto enqueue = [&](hipStream_t st) -> int {
+        int64_t measured = 0, reduced = 0;
+        const size_t nl = dp->sp.launch_tmpl.size();
+        for (size_t l = 0; l < nl; ++l) {
+            const int t = dp->sp.launch_tmpl[l];
+            const int64_t off = dp->sp.launch_offset[l];
+            PassShape shp = dp->shape;
+            shp.mats = static_cast<const float*>(dp->d_mats);
+            shp.writes = dp->sp.passes[t].writes;
+            HIP_TRY((launch_pass<T>(shp, psi, static_cast<const DevPass*>(dp->d_passes),
+                                    static_cast<const DevStage*>(dp->d_stages),
+                                    static_cast<const DevOp<T>*>(dp->d_ops), t, dp->tiles_per_wg,
+                                    dp->nwg, part, off, ch, st)));
+            for (int64_t s : dp->meas[t]) measured = std::max(measured, s + off + 1);
+            if (measured - reduced >= ch / 2 || (l + 1 == nl && measured > reduced)) {
+                HIP_TRY(launch_reduce(part, dp->nwg, ch, reduced, measured - reduced, P, N, st));
+                reduced = measured;
+            }
         }
+        if (reduced != total) {
+            std::ostringstream os;
+            os << "internal: plan measured " << reduced << " of " << total << " steps";
+            return fail(SPIN_EUNSUPPORTED, os.str());
+        }
+        return SPIN_OK;
+    };
+    if (graph) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        return run_as_graph(GraphKey{dp.get(), psi, P, N, part, dev}, enqueue, st);
     }
-    if (reduced != total) {
-        std::ostringstream os;
-        os << "internal: plan measured " << reduced << " of " << total << " steps";
-        return fail(SPIN_EUNSUPPORTED, os.str());
-    }
-    return SPIN_OK;
+    return enqueue(st);
 }
 
 }  // namespace spinqp
@@ -622,6 +709,7 @@ int spin_trotter_evolve(void* psi, int32_t prec, int32_t M, const spin_coupling*
 }
 
 void spin_release_caches(void) {
+    release_graphs();
     release_batch_caches();
     release_tune_cache();
     std::lock_guard<std::mutex> lk(g_mu);

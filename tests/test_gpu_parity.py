@@ -408,6 +408,8 @@ PROFILE = [
      {"tile_bits": 12, "reg_bits": 4}),
     ("tiled-chain17", 17, workloads.chain(17), 0.1, 20, 0, {}),
     ("unfused-ladder8", 8, workloads.ladder(4), 0.1, 4, 0, {"schedule": 1}),
+    ("tiled-ladder16-nomerge-backwards", 16, workloads.ladder(8, a_over_b=0.5), -0.05, 9, 3,
+     {"tile_bits": 12, "no_merge": 1}),
 ]
 
 
@@ -424,6 +426,32 @@ def test_profile_matches_oracle(prec, case):
     assert np.abs(Pg - Pw).max() < TOL_P[prec]
     assert np.abs(Ng - Nw).max() < TOL_P[prec]
     assert_state_close(psig, psiw, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_profile_chunked_equals_one_call(prec):
+    """Two profile calls of 25 steps continue one state like one call of 50
+    (different plans, so equal up to rounding)."""
+    import torch
+    from gpu_helpers import gpu_profile
+    M, J, dt = 18, workloads.ladder(9), 0.05
+    note("profile chunked", prec)
+    P1, N1, psi1 = gpu_profile(prec, M, J, dt, 50, 0, 4)
+    psi = gpu_state(prec, M, 0, 4)
+    parts = []
+    for _ in range(2):
+        Pall = torch.zeros(26 * M, dtype=torch.float64, device="cuda")
+        spq.spin_trotter_evolve_profile(psi, M, J, dt, 25, Pall)
+        parts.append(Pall)
+    torch.cuda.synchronize()
+    a, b = (t.cpu().numpy().reshape(26, M) for t in parts)
+    P2 = np.concatenate([a, b[1:]])
+    # the same state read twice: the first call reads a site once its last
+    # factor has run (other sites' factors may follow, exact in exact
+    # arithmetic), the second at entry; equal up to the state's rounding
+    assert np.abs(a[-1] - b[0]).max() < TOL_P[prec]
+    assert np.abs(P2 - P1).max() < TOL_P[prec]
+    assert_state_close(psi.cpu().numpy().astype(np.complex128), psi1, prec)
 
 
 def test_profile_rejects_matrix_engine_and_null_output():
@@ -528,3 +556,33 @@ def test_fig3a_entangled_vs_product_states_M14():
     note("fig3a rms mean630", rms(mean))
     assert rms(mean) < 2 * sigma
     assert rms(mean) < np.median(prod) / 3
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_graph_replays_equal_eager_runs(prec):
+    """use_graph: the captured launch sequence, replayed several times with
+    eager work and synchronisations in between, gives bitwise the eager
+    result every time (single-site and all-site profile)."""
+    import torch
+    M, J, dt, steps = 18, workloads.ladder(9), 0.05, 30
+    note("graph replays", prec)
+    eager_P, _, eager_psi, _ = gpu_evolve(prec, M, J, dt, steps, 0, seed=6)
+    from gpu_helpers import gpu_profile
+    eager_Pall, _, eager_psi2 = gpu_profile(prec, M, J, dt, steps, 0, 6)
+    psi = torch.empty(2 ** M, dtype=torch_dtype(prec), device="cuda")
+    P = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+    Pall = torch.zeros((steps + 1) * M, dtype=torch.float64, device="cuda")
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    g = spq.Options(use_graph=1)
+    for rep in range(3):
+        spq.spin_init_random_phase(psi, M, 0, 6)
+        spq.spin_trotter_evolve_ex(psi, M, J, dt, steps, 0, P, None, g)
+        spq.spin_local_polarization(psi, M, 3, out)       # eager work on the same stream
+        torch.cuda.synchronize()
+        assert np.array_equal(P.cpu().numpy(), eager_P), rep
+        assert np.array_equal(psi.cpu().numpy().astype(np.complex128), eager_psi), rep
+        spq.spin_init_random_phase(psi, M, 0, 6)
+        spq.spin_trotter_evolve_profile(psi, M, J, dt, steps, Pall, None, g)
+        torch.cuda.synchronize()
+        assert np.array_equal(Pall.cpu().numpy().reshape(steps + 1, M), eager_Pall), rep
+        assert np.array_equal(psi.cpu().numpy().astype(np.complex128), eager_psi2), rep
