@@ -259,8 +259,10 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  * States small enough for one workgroup have a single shape (one trial).
  * A trial of a few steps runs on a short plan whose passes per step differ
  * from a long run's (the plan repeats in blocks of tens of steps), so the
- * ranking is the trial's time per pass launch times the passes per step of
- * the candidate's plan for a 1000-step run (or trial_steps, if longer).
+ * candidates within 20% of the fastest trial (at most three) are ranked by
+ * their trial time per pass launch times the passes per step of their plan
+ * for a 1000-step run (or trial_steps, if longer); the others keep their
+ * trial time per step.
  * Planning is done before each timed trial and is not part of the times.
  * Errors as spin_trotter_evolve_ex; SPIN_ENOMEM if the scratch state cannot
  * be allocated; SPIN_EUNSUPPORTED if no candidate ran.
@@ -271,11 +273,12 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  */
 typedef struct {
     spin_options opt;          /* the candidate */
-    double ms_per_step;        /* ranking: trial time per pass launch x passes_per_step
-                                  (the trial time per step for one-workgroup states);
-                                  -1 if the candidate failed */
+    double ms_per_step;        /* ranking: for the refined candidates, trial time per
+                                  pass launch x passes_per_step; otherwise the trial
+                                  time per step; -1 if the candidate failed */
     double trial_ms_per_step;  /* measured time per step of the trial itself */
-    double passes_per_step;    /* of the plan of a 1000-step run (host planning) */
+    double passes_per_step;    /* of the 1000-step plan (refined candidates), else of
+                                  the trial's plan */
     int32_t status;            /* spin_status of the candidate's trial */
     int32_t reserved_;
 } spin_tune_result;

@@ -191,16 +191,20 @@ extern "C" int spin_autotune(int32_t prec, int32_t M, const spin_coupling* J, in
         // (host planning only), whose repeating block a short trial's plan
         // does not reach.
         const int64_t long_steps = std::max<int64_t>(trial_steps, kTuneLongSteps);
-        int nres = 0, ibest = -1;
+        // 1) every candidate: a timed trial of trial_steps steps
+        struct Trial {
+            int status = SPIN_OK;
+            double trial = -1.0;       // ms per step of the trial
+            double per_launch = -1.0;  // ms per pass launch of the trial (tiled path)
+            double pps = 0.0;          // passes per step reported
+        };
+        std::vector<Trial> tr(cand.size());
         for (size_t ci = 0; ci < cand.size(); ++ci) {
-            Tuned& t = cand[ci];
-            spin_options o = to_options(t);
-            spin_plan_info info, linfo;
+            spin_options o = to_options(cand[ci]);
+            spin_plan_info info;
             std::memset(&info, 0, sizeof info);
-            std::memset(&linfo, 0, sizeof linfo);
             int crc = spin_prepare_plan(prec, M, J, K, dt, trial_steps, observed_site, &o);
             if (crc == SPIN_OK) crc = spin_describe_plan(prec, M, J, K, dt, trial_steps, observed_site, &o, &info);
-            if (crc == SPIN_OK) crc = spin_describe_plan(prec, M, J, K, dt, long_steps, observed_site, &o, &linfo);
             if (crc == SPIN_OK) crc = spin_init_random_phase(b.psi, prec, M, 0, 1, st);
             if (crc == SPIN_OK)   // warm-up
                 crc = spin_trotter_evolve_ex(b.psi, prec, M, J, K, dt, trial_steps, observed_site, b.P, b.N, &o, st);
@@ -212,22 +216,48 @@ extern "C" int spin_autotune(int32_t prec, int32_t M, const spin_coupling* J, in
                     hipEventElapsedTime(&ms, b.e0, b.e1) != hipSuccess)
                     return fail(SPIN_EHIP, "autotune timing failed");
             }
-            const double trial = crc == SPIN_OK ? double(ms) / double(trial_steps) : -1.0;
-            // one workgroup holds the state: one launch, nothing to scale
-            const bool tiled = crc == SPIN_OK && info.path == 2 && info.launches > 0;
-            t.ms_per_step = !tiled ? trial
-                                   : double(ms) / double(info.launches) * linfo.passes_per_step;
-            if (crc == SPIN_OK && (ibest < 0 || t.ms_per_step < cand[ibest].ms_per_step)) ibest = int(ci);
-            if (nres < cap) {
-                spin_tune_result& r = results[nres];
-                std::memset(&r, 0, sizeof r);
-                r.opt = o;
-                r.ms_per_step = t.ms_per_step;
-                r.trial_ms_per_step = trial;
-                r.passes_per_step = tiled ? linfo.passes_per_step : info.passes_per_step;
-                r.status = crc;
+            tr[ci].status = crc;
+            tr[ci].pps = info.passes_per_step;
+            if (crc == SPIN_OK) {
+                tr[ci].trial = double(ms) / double(trial_steps);
+                // one workgroup holds the state: one launch, nothing to scale
+                if (info.path == 2 && info.launches > 0) tr[ci].per_launch = double(ms) / double(info.launches);
             }
-            ++nres;
+            cand[ci].ms_per_step = tr[ci].trial;
+        }
+        // 2) the candidates within 20% of the fastest trial (at most three):
+        //    time per launch x passes per step of their long-run plan
+        //    (host planning only)
+        std::vector<int> order;
+        for (size_t ci = 0; ci < cand.size(); ++ci)
+            if (tr[ci].status == SPIN_OK) order.push_back(int(ci));
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tr[a].trial < tr[c].trial; });
+        int ibest = order.empty() ? -1 : order[0];
+        double best_pred = order.empty() ? 0.0 : tr[order[0]].trial;
+        for (size_t n = 0; n < order.size() && n < 3; ++n) {
+            const int ci = order[n];
+            if (tr[ci].trial > 1.2 * tr[order[0]].trial || tr[ci].per_launch < 0) continue;
+            spin_options o = to_options(cand[ci]);
+            spin_plan_info linfo;
+            std::memset(&linfo, 0, sizeof linfo);
+            if (spin_describe_plan(prec, M, J, K, dt, long_steps, observed_site, &o, &linfo) != SPIN_OK) continue;
+            tr[ci].pps = linfo.passes_per_step;
+            cand[ci].ms_per_step = tr[ci].per_launch * linfo.passes_per_step;
+            if (n == 0 || cand[ci].ms_per_step < best_pred) {
+                best_pred = cand[ci].ms_per_step;
+                ibest = ci;
+            }
+        }
+        int nres = 0;
+        for (size_t ci = 0; ci < cand.size(); ++ci, ++nres) {
+            if (nres >= cap) continue;
+            spin_tune_result& r = results[nres];
+            std::memset(&r, 0, sizeof r);
+            r.opt = to_options(cand[ci]);
+            r.ms_per_step = cand[ci].ms_per_step;
+            r.trial_ms_per_step = tr[ci].trial;
+            r.passes_per_step = tr[ci].pps;
+            r.status = tr[ci].status;
         }
         if (n_results) *n_results = nres;
         if (hipStreamSynchronize(st) != hipSuccess) return fail(SPIN_EHIP, "hipStreamSynchronize failed");
