@@ -246,6 +246,32 @@ def cpu_baseline(w, n_couplings=None):
                 seconds=sec)
 
 
+def cpu_single_core(w, M=26, n_couplings=20):
+    """The same C oracle on one thread (a child process with
+    OMP_NUM_THREADS=1): one Strang step of the first n_couplings couplings
+    among sites below M on an M=26 state (1 GiB, beyond the host caches)."""
+    import subprocess
+    code = (
+        "import json,sys,time\n"
+        f"sys.path.insert(0,{ROOT!r})\n"
+        "from oracle import cref\n"
+        "cref.build(force=False)\n"
+        f"J={[c for c in w['J'] if max(c[0], c[1]) < M][:n_couplings]!r}\n"
+        f"psi=cref.init_random_phase({M},{w['polarized']},{w['seed']})\n"
+        "t0=time.perf_counter()\n"
+        f"cref.trotter_run(psi,{M},J,{w['dt']!r},1,{w['observed']})\n"
+        "print(json.dumps({'seconds':time.perf_counter()-t0}))\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=600, check=True)
+    sec = json.loads(out.stdout.strip().splitlines()[-1])["seconds"]
+    nfac = 2 * n_couplings
+    return dict(value=nfac * 2 ** M / sec, unit="amplitude-updates/s", cores=1, kind="oracle",
+                sample=f"one Strang step of the first {n_couplings} couplings ({nfac} factor "
+                       f"applications, 2 observables) of an M={M} complex128 state, one thread; "
+                       f"{sec:.2f} s")
+
+
 def copy_probe(torch, gib=4, reps=5):
     """Plain device-to-device copy of `gib` GiB (torch's copy kernel): the
     reference for the HBM byte counters and the achievable copy bandwidth."""
@@ -448,6 +474,7 @@ def main():
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(w)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline_single_core"] = cpu_single_core(w)
     print(json.dumps(out), flush=True)
 
 

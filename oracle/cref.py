@@ -55,6 +55,11 @@ def init_random_phase(M: int, n: int, seed: int) -> np.ndarray:
 def trotter_run(psi: np.ndarray, M: int, couplings, dt: float, n_steps: int, observed: int):
     """Evolve ``psi`` (complex128, modified in place); returns (P, N)."""
     assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.size == 2 ** M
+    if not 0 <= observed < M:
+        raise ValueError("observed site out of range")
+    for c in couplings:     # the C loop indexes by site without checks
+        if not (0 <= c[0] < M and 0 <= c[1] < M and c[0] != c[1]):
+            raise ValueError(f"coupling {c} out of range for M={M}")
     K = len(couplings)
     ci = np.array([c[0] for c in couplings] or [0], dtype=np.int32)
     cj = np.array([c[1] for c in couplings] or [0], dtype=np.int32)
