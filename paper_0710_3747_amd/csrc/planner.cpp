@@ -119,7 +119,7 @@ struct Sched {
     double closure(Mask T, std::vector<int>* applied) const {
         std::vector<int> h = head;
         std::vector<int> work;
-        int nmeas = 0;
+        int nmeas = 0, nnorm = 0;
         double score = 0;
         auto consider = [&](int s) {
             if (h[s] < int(site_ops[s].size())) {
@@ -136,6 +136,12 @@ struct Sched {
             const Op& op = ops[n];
             if (op.kind == 1) {
                 if (nmeas >= max_meas) continue;
+                // with every site observed, the observed site's op also
+                // carries the step's norm: at most kMaxMeas norm slots
+                if (all_sites && op.i == observed) {
+                    if (nnorm >= kMaxMeas) continue;
+                    ++nnorm;
+                }
                 ++nmeas;
                 score += 1e-3;
             } else {

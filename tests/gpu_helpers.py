@@ -52,10 +52,11 @@ def assert_state_close(got, want, prec):
     assert err < TOL_PSI[prec], f"state rel err {err:.3e}"
 
 
-def gpu_profile(prec, M, J, dt, steps, polarized=0, seed=1, opts=None, psi0=None):
+def gpu_profile(prec, M, J, dt, steps, polarized=0, seed=1, opts=None, psi0=None,
+                keep_state=True):
     """All-site profile through spin_trotter_evolve_profile.
 
-    Returns (Pall (steps+1, M), N, psi_numpy)."""
+    Returns (Pall (steps+1, M), N, psi_numpy or None)."""
     import torch
     psi = gpu_state(prec, M, polarized, seed, psi0)
     Pall = torch.full(((steps + 1) * M,), float("nan"), dtype=torch.float64, device="cuda")
@@ -63,5 +64,5 @@ def gpu_profile(prec, M, J, dt, steps, polarized=0, seed=1, opts=None, psi0=None
     o = spq.Options(**opts) if opts else None
     spq.spin_trotter_evolve_profile(psi, M, J, dt, steps, Pall, N, o)
     torch.cuda.synchronize()
-    return (Pall.cpu().numpy().reshape(steps + 1, M), N.cpu().numpy(),
-            psi.cpu().numpy().astype(np.complex128))
+    out = psi.cpu().numpy().astype(np.complex128) if keep_state else None
+    return Pall.cpu().numpy().reshape(steps + 1, M), N.cpu().numpy(), out

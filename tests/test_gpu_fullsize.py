@@ -180,6 +180,26 @@ def test_maximum_sizes_single_bond(prec, M):
     assert np.abs(N - 1).max() < (1e-10 if prec == C128 else 1e-4)
 
 
+@pytest.mark.parametrize("prec,M", [(C64, 34), (C128, 33)])
+def test_maximum_sizes_profile_single_bond(prec, M):
+    """All-site profile at the largest states: the bond's two sites follow
+    (1 +- cos bt)/2, every other site stays at zero, the norm at one."""
+    import torch
+    if free_mem_gib() < 130:
+        pytest.skip("not enough device memory for a 128 GiB state")
+    from gpu_helpers import gpu_profile
+    b, dt, steps = 0.9, 0.1, 4
+    note("max size profile", prec, M)
+    Pall, N, _ = gpu_profile(prec, M, [(0, M - 1, 0.2, b)], dt, steps, 0, 1, keep_state=False)
+    c = np.cos(b * np.arange(steps + 1) * dt)
+    tol = TOL_P[prec]
+    assert np.abs(Pall[:, 0] - 0.5 * (1 + c)).max() < tol
+    assert np.abs(Pall[:, M - 1] - 0.5 * (1 - c)).max() < tol
+    assert np.abs(Pall[:, 1:M - 1]).max() < tol
+    assert np.abs(N - 1).max() < (1e-10 if prec == C128 else 1e-4)
+    torch.cuda.empty_cache()
+
+
 def test_mfma_engine_ladder_2x15_sectors_and_vs_butterflies():
     """Matrix engine at M = 30 (8 GiB complex64): sectors with <= 2 spins
     down against the oracle, and P against the butterfly path."""
@@ -206,7 +226,7 @@ def test_profile_ladder_2x15_free_fermions_every_site(prec):
     M = 2 * L
     J = workloads.ladder(L, bx=1.0, by=0.0)
     note("profile free fermion M=30", prec)
-    Pall, N, _ = gpu_profile(prec, M, J, dt, steps, 0, 5)
+    Pall, N, _ = gpu_profile(prec, M, J, dt, steps, 0, 5, keep_state=False)
     bonds = [(i, j, b) for (i, j, a, b) in J if i < L and j < L]
     want = ed.free_fermion_profile(L, bonds, dt, steps)
     sigma = 2.0 ** (-(M - 1) / 2)

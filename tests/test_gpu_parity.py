@@ -454,6 +454,23 @@ def test_profile_chunked_equals_one_call(prec):
     assert_state_close(psi.cpu().numpy().astype(np.complex128), psi1, prec)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,steps", [(23, 50), (28, 4)])
+def test_profile_sparse_couplings_many_steps_per_pass(prec, M, steps):
+    """One bond between the end sites: a pass spans many steps, so the norm
+    slots per pass (one per step) bound the pass, not the observables.  The
+    bond's sites follow (1 +- cos bt)/2, the rest stay at zero."""
+    from gpu_helpers import gpu_profile
+    b, dt = 0.9, 0.1
+    note("profile sparse", prec, M, steps)
+    Pall, N, _ = gpu_profile(prec, M, [(0, M - 1, 0.2, b)], dt, steps, 0, 2, keep_state=False)
+    c = np.cos(b * np.arange(steps + 1) * dt)
+    assert np.abs(Pall[:, 0] - 0.5 * (1 + c)).max() < TOL_P[prec]
+    assert np.abs(Pall[:, M - 1] - 0.5 * (1 - c)).max() < TOL_P[prec]
+    assert np.abs(Pall[:, 1:M - 1]).max() < TOL_P[prec]
+    assert np.abs(N - 1).max() < TOL_P[prec]
+
+
 def test_profile_rejects_matrix_engine_and_null_output():
     import torch
     psi = gpu_state(C64, 16)
