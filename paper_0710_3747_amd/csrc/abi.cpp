@@ -776,6 +776,21 @@ int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double d
             if (profile) pp.max_meas = kMaxMeasProfile;
             hp->sp = plan_stream_best(M, Jv, dt, n_steps, observed, merge, pp);
         }
+        // encode the tables as the evolve call would (nothing is uploaded),
+        // so that the host-only calls report the errors that call would
+        auto encode_all = [&](auto tag) {
+            using T = decltype(tag);
+            DevTables<T> tb;
+            if (hp->path == 1) {
+                encode_pass<T>(hp->rp.prologue, M, observed, tb, true, 0, profile);
+                encode_pass<T>(hp->rp.step, M, observed, tb, true, 0, profile);
+            } else if (hp->path == 2) {
+                for (const HostPass& p : hp->sp.passes)
+                    encode_pass<T>(p, M, observed, tb, false, hp->sh.engine, profile);
+            }
+        };
+        if (prec == SPIN_C64) encode_all(float{});
+        else encode_all(double{});
     } catch (const std::exception& e) {
         return fail(SPIN_EUNSUPPORTED, std::string("planning failed: ") + e.what());
     }

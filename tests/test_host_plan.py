@@ -220,3 +220,36 @@ def test_batch_rejects_bad_init_and_basis_index():
     assert rc == spq.SPIN_EINVAL and "basis index" in spq.spin_last_error()
     rc = lib.spin_trotter_evolve_batch(pr, 1, arr, K, spq.SPIN_C64, 0.1, 3, 7, None)
     assert rc == spq.SPIN_EINVAL and "init" in spq.spin_last_error()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_graphs_plan_and_encode(seed):
+    """Random coupling graphs, sizes, shapes and step counts: the host-only
+    description plans and encodes the tables exactly as the evolve call
+    would, and must succeed (single site and all-site profile)."""
+    rng = np.random.default_rng(seed)
+    for _ in range(4):
+        prec = [spq.SPIN_C64, spq.SPIN_C128][int(rng.integers(2))]
+        M = int(rng.integers(2, 23))
+        K = int(rng.integers(0, 3 * M))
+        J = []
+        for _ in range(K):
+            i, j = (int(x) for x in rng.integers(0, M, size=2))
+            if i != j:
+                a = float(rng.uniform(-1, 1)) if rng.integers(3) == 0 else 0.0
+                J.append((i, j, a, float(rng.uniform(-2, 2))))
+        steps = int(rng.integers(0, 40))
+        opts = {}
+        if M > 14 and rng.integers(2):
+            opts = {"tile_bits": 12, "reg_bits": 4}
+        o = spq.Options(**opts)
+        for obs in (int(rng.integers(M)), spq.SPIN_ALL_SITES):
+            spq.spin_describe_plan(prec, M, J, 0.05, steps, obs, o)
+
+
+def test_profile_plan_encodes_with_many_steps_per_pass():
+    """One bond between the end sites: a profile pass spans many steps; its
+    norm slots must stay within the pass's capacity (regression)."""
+    for prec, M, steps in [(spq.SPIN_C64, 28, 4), (spq.SPIN_C128, 24, 50), (spq.SPIN_C64, 34, 4)]:
+        info = spq.spin_describe_plan(prec, M, [(0, M - 1, 0.2, 0.9)], 0.1, steps, spq.SPIN_ALL_SITES)
+        assert info["path"] == 2
