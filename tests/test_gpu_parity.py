@@ -603,3 +603,35 @@ def test_graph_replays_equal_eager_runs(prec):
         torch.cuda.synchronize()
         assert np.array_equal(Pall.cpu().numpy().reshape(steps + 1, M), eager_Pall), rep
         assert np.array_equal(psi.cpu().numpy().astype(np.complex128), eager_psi2), rep
+
+
+def _random_graph(rng, M):
+    J = []
+    for _ in range(int(rng.integers(1, 3 * M))):
+        i, j = (int(x) for x in rng.integers(0, M, size=2))
+        if i != j:
+            a = float(rng.uniform(-1, 1)) if rng.integers(3) == 0 else 0.0
+            J.append((i, j, a, float(rng.uniform(-2, 2))))
+    return J
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", range(4))
+def test_random_graphs_match_oracle(prec, seed):
+    """Seeded random coupling graphs (any pairs, Ising parts, repeated
+    pairs), tiled sizes: P, N and the state against the oracle's loop, and
+    the all-site profile against the oracle's profile."""
+    from gpu_helpers import gpu_profile
+    rng = np.random.default_rng(100 + seed)
+    M = int(rng.integers(15, 18))
+    J = _random_graph(rng, M)
+    obs, pol = int(rng.integers(M)), int(rng.integers(M))
+    dt, steps = float(rng.uniform(-0.1, 0.1)), int(rng.integers(3, 10))
+    note("random graph", prec, seed, M, len(J), steps)
+    P, N, psi, _ = gpu_evolve(prec, M, J, dt, steps, obs, polarized=pol, seed=seed)
+    Pw, Nw, psiw = oracle_run(M, J, dt, steps, obs, pol, seed)
+    assert np.abs(P - Pw).max() < TOL_P[prec]
+    assert_state_close(psi, psiw, prec)
+    Pg, _, _ = gpu_profile(prec, M, J, dt, steps, pol, seed, keep_state=False)
+    Pp, _, _ = oracle.trotter_profile(oracle.random_phase_state(M, pol, seed), M, J, dt, steps)
+    assert np.abs(Pg - Pp).max() < TOL_P[prec]
