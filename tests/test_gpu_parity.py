@@ -635,3 +635,28 @@ def test_random_graphs_match_oracle(prec, seed):
     Pg, _, _ = gpu_profile(prec, M, J, dt, steps, pol, seed, keep_state=False)
     Pp, _, _ = oracle.trotter_profile(oracle.random_phase_state(M, pol, seed), M, J, dt, steps)
     assert np.abs(Pg - Pp).max() < TOL_P[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_random_graphs_match_oracle(prec):
+    """A batch of seeded random graphs of uneven size (LDS-held and gang
+    problems, random observed and polarised sites) against the oracle's loop,
+    problem by problem."""
+    import torch
+    rng = np.random.default_rng(7)
+    steps, dt = 12, 0.04
+    probs = []
+    for r in range(10):
+        M = int(rng.integers(3, 18))
+        probs.append(dict(psi=torch.empty(2 ** M, dtype=torch_dtype(prec), device="cuda"), M=M,
+                          couplings=_random_graph(rng, M), observed_site=int(rng.integers(M)),
+                          polarized_site=int(rng.integers(M)), seed=50 + r,
+                          P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
+    note("batch random graphs", prec, [p["M"] for p in probs])
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init=spq.SPIN_INIT_RANDOM_PHASE)
+    torch.cuda.synchronize()
+    for p in probs:
+        Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, p["observed_site"],
+                                 p["polarized_site"], p["seed"])
+        assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec], p["M"]
+        assert_state_close(p["psi"].cpu().numpy().astype(np.complex128), psiw, prec)
