@@ -373,9 +373,9 @@ __device__ __forceinline__ int64_t next_submask(int64_t cur, int64_t mask) {
 // Gather / scatter of a lane's 2^R registers in Gray-code order: register
 // j = i ^ (i >> 1) sits at pb ^ (xor of rbit[q] over the set bits q of j),
 // and consecutive Gray codes differ in bit ctz(i).
-template <int R, typename C>
+template <int R, typename C, typename Stage>
 __device__ __forceinline__ void gather(C (&v)[1 << R], const char* lds, uint32_t pb,
-                                       const DevStage& S) {
+                                       const Stage& S) {
     uint32_t a = pb;
     v[0] = *reinterpret_cast<const C*>(lds + a);
 #pragma unroll
@@ -385,9 +385,9 @@ __device__ __forceinline__ void gather(C (&v)[1 << R], const char* lds, uint32_t
     }
 }
 
-template <int R, typename C>
+template <int R, typename C, typename Stage>
 __device__ __forceinline__ void scatter(const C (&v)[1 << R], char* lds, uint32_t pb,
-                                        const DevStage& S) {
+                                        const Stage& S) {
     uint32_t a = pb;
     *reinterpret_cast<C*>(lds + a) = v[0];
 #pragma unroll
@@ -396,6 +396,13 @@ __device__ __forceinline__ void scatter(const C (&v)[1 << R], char* lds, uint32_
         *reinterpret_cast<C*>(lds + a) = v[i ^ (i >> 1)];
     }
 }
+
+// Register offsets of a stage read into scalar registers together with its
+// lane offsets (one round trip for both before the gather).
+template <int R>
+struct RegBits {
+    uint32_t rbit[R];
+};
 
 // Runs ops from index o up to the stage end o1 or the next observable op
 // (whichever comes first) on the lane's registers; returns the index of
@@ -600,8 +607,11 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
 
         for (int si = 0; si < P.nstage; ++si) {
             const DevStage& S = stages[P.stage0 + si];
+            RegBits<R> rb;
+#pragma unroll
+            for (int b = 0; b < R; ++b) rb.rbit[b] = S.rbit[b];
             const uint32_t pb = stage_base(S, tid);
-            if (si > 0) gather<R>(v, ldsb, pb, S);
+            if (si > 0) gather<R>(v, ldsb, pb, rb);
             const int sign = tile_sign ^ (S.obs_tq >= 0 ? ((tid >> S.obs_tq) & 1) : 0);
             const int o1 = S.op0 + S.nop;
             int o = S.op0;
@@ -672,7 +682,7 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
             if (si + 1 < P.nstage) {
                 // A lane scatters to exactly the LDS slots the next stage's
                 // lanes gather after the barrier.
-                scatter<R>(v, ldsb, pb, S);
+                scatter<R>(v, ldsb, pb, rb);
                 lds_barrier();
             }
         }
