@@ -429,6 +429,21 @@ def test_profile_matches_oracle(prec, case):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M", [1, 2, 3, 5])
+def test_profile_smallest_states(prec, M):
+    """The whole-state kernel's profile at the smallest sizes (fewer sites
+    than register bits), element by element against the oracle."""
+    from gpu_helpers import gpu_profile
+    J = [] if M == 1 else [(i, (i + 1) % M, 0.4, 1.1) for i in range(M - 1)]
+    note("profile small", prec, M)
+    Pg, Ng, psig = gpu_profile(prec, M, J, 0.2, 7, M - 1, 3)
+    Pw, Nw, psiw = oracle.trotter_profile(oracle.random_phase_state(M, M - 1, 3), M, J, 0.2, 7)
+    assert np.abs(Pg - Pw).max() < TOL_P[prec]
+    assert np.abs(Ng - Nw).max() < TOL_P[prec]
+    assert_state_close(psig, psiw, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_profile_chunked_equals_one_call(prec):
     """Two profile calls of 25 steps continue one state like one call of 50
     (different plans, so equal up to rounding)."""
