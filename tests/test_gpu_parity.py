@@ -528,7 +528,7 @@ def test_batch_product_init_matches_single_runs(prec):
     note("batch product init", prec)
     steps, dt = 20, 0.03
     probs, singles = [], []
-    for idx, (M, seed) in enumerate([(10, 4), (12, 9), (16, 2), (18, 31)]):
+    for idx, (M, seed) in enumerate([(3, 6), (10, 4), (12, 9), (16, 2), (18, 31)]):
         J = workloads.star(M, 40 + idx)
         pol = idx % M
         psi = torch.zeros(2 ** M, dtype=torch_dtype(prec), device="cuda")
