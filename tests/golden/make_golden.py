@@ -10,7 +10,11 @@ ensemble_ladder2x7_by0p1.txt: the exact infinite-temperature ensemble
 polarisation P^ens_11(t) of Eq. (1) (exact diagonalisation, oracle.ed) for
 the 14-spin ladder of Fig. 3(a): XY couplings, b_x = 1 on the legs, b_y =
 b_x/10 on the rungs, site 0 polarised and observed, t = 0.05 k, k = 0..300.
-About three minutes of CPU; ``python tests/golden/make_golden.py phase``
+ensemble_star14_dipolar.txt: the same for the dipolar star of Fig. 3(b):
+M = 14, every pair coupled with b ~ N(0, 1) and a = -2b, site 0 polarised
+and observed, t = 0.02 k, k = 0..250.
+
+About three minutes of CPU each; ``python tests/golden/make_golden.py phase``
 rewrites only the phase vectors.
 """
 import os
@@ -35,6 +39,19 @@ def write_fig3a_ensemble():
         f.write("\n".join(lines) + "\n")
 
 
+def write_fig3b_ensemble():
+    import numpy as np
+    from oracle import ed
+    J = workloads.star(14, 77, var_center=1.0, var_other=1.0, a_over_b=-2.0)
+    times = 0.02 * np.arange(251)
+    P = ed.ensemble_P_exact(14, J, times, 0, 0)
+    lines = ["# t P_ens  (Fig. 3(b) dipolar star M=14: every pair, b ~ N(0,1) (workloads.star seed 77),"
+             " a = -2b; exact ensemble of Eq. (1))"]
+    lines += [f"{float(t):.17g} {float(p):.17g}" for t, p in zip(times, P)]
+    with open(os.path.join(HERE, "ensemble_star14_dipolar.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     seeds = [0, 1, 2, 5, 33, 1000, 123456789, 2 ** 63 + 17, MASK]
     rs = [0, 1, 2, 3, 7, 100, 511, 4095, 65535, 2 ** 20 - 1, 2 ** 29 - 1, 2 ** 32 + 5, 2 ** 40 + 1]
@@ -51,3 +68,4 @@ if __name__ == "__main__":
     main()
     if sys.argv[1:] != ["phase"]:
         write_fig3a_ensemble()
+        write_fig3b_ensemble()

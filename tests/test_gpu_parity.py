@@ -675,3 +675,32 @@ def test_batch_random_graphs_match_oracle(prec):
                                  p["polarized_site"], p["seed"])
         assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec], p["M"]
         assert_state_close(p["psi"].cpu().numpy().astype(np.complex128), psiw, prec)
+
+
+def test_fig3b_dipolar_star_entangled_and_product_states_M14():
+    """Fig. 3(b), qualitatively: in the dipolar star (every pair coupled,
+    b ~ N(0, 1), a = -2b) the cross terms of Eq. (3) decay, so one
+    entangled state follows the stored exact ensemble within
+    2 * 2^-(M-1)/2 RMS and even one product state stays within 6 times
+    that, unlike the ladder of Fig. 3(a) (test above) where it is off by
+    more than 15 times."""
+    import os
+    import torch
+    M, dt, steps = 14, 0.02, 250
+    J = workloads.star(M, 77, var_center=1.0, var_other=1.0, a_over_b=-2.0)
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "ensemble_star14_dipolar.txt"))
+    assert np.allclose(gold[:, 0], dt * np.arange(steps + 1))
+    Pens = gold[:, 1]
+    sigma = 2.0 ** (-(M - 1) / 2)
+    rms = lambda P: float(np.sqrt(np.mean((P - Pens) ** 2)))
+    ent, prod = [], []
+    for seed in range(4):
+        Pe, _, _, _ = gpu_evolve(C128, M, J, dt, steps, 0, seed=seed, keep_state=False)
+        psi = torch.empty(2 ** M, dtype=torch.complex128, device="cuda")
+        spq.spin_init_product(psi, M, 0, seed)
+        Pp, _, _, _ = gpu_evolve(C128, M, J, dt, steps, 0, psi=psi, keep_state=False)
+        ent.append(rms(Pe))
+        prod.append(rms(Pp))
+    note("fig3b rms ent", ent, "prod", prod, "sigma", sigma)
+    assert max(ent) < 2 * sigma
+    assert max(prod) < 6 * sigma
