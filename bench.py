@@ -288,8 +288,9 @@ def copy_probe(torch, gib=4, reps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     gbs = 2 * n * 4 / (ms / 1e3) / 1e9
-    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": ms,
-                      "copy_GBs": gbs}), flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": ms, "copy_GBs": gbs}
 
 
 def main():
@@ -327,7 +328,7 @@ def main():
     import paper_0710_3747_amd as spq
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
-        copy_probe(torch)
+        print(json.dumps(copy_probe(torch)), flush=True)
         return
     spq.load_library()
     if args.workload == "ensemble":
@@ -428,6 +429,12 @@ def main():
         out["norm_drift_fp64"] = float(np.abs(res64["N"] - 1).max())
     if tuned:
         out["autotune"] = tuned
+    if args.workload == "ladder_2x15":
+        # second denominator: what a plain device copy reaches on this GPU
+        # (torch's copy kernel, 4 GiB read + 4 GiB written), outside the timed region
+        cp = copy_probe(torch)
+        out["roofline"]["copy_GBs"] = cp["copy_GBs"]
+        out["roofline"]["frac_of_copy"] = s["achieved_gbs"] / cp["copy_GBs"]
     if args.workload == "ladder_2x15" and res32 is not None and args.engine_steps > 0:
         # stage arithmetic on FP32 MFMA (each stage's factors as one dense
         # 32 x 32 complex matrix) against the VALU butterflies, same shape
