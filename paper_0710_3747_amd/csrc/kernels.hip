@@ -540,6 +540,29 @@ __device__ __forceinline__ double dpp_add(double v) {
     return v + __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
+// Squared magnitudes of the lane's 2^R registers in FP64: their total and,
+// for each register bit b, the half sum over registers with bit b set.
+// Pairwise: the sums over bit b's pairs feed bit b+1 (2^R - 1 adds for the
+// total, 2^R - 1 - R for the half sums).
+template <int R, typename C>
+__device__ __forceinline__ void reg_half_sums(const C (&v)[1 << R], double& tot, double (&half)[R]) {
+    double w[1 << R];
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j)
+        w[j] = double(v[j].x) * double(v[j].x) + double(v[j].y) * double(v[j].y);
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+        const int n = (1 << R) >> (b + 1);    // pairs at this level
+        double h = w[1];
+#pragma unroll
+        for (int i = 1; i < n; ++i) h += w[2 * i + 1];
+        half[b] = h;
+#pragma unroll
+        for (int i = 0; i < n; ++i) w[i] = w[2 * i] + w[2 * i + 1];
+    }
+    tot = w[0];
+}
+
 __device__ __forceinline__ double wave_sum_last(double v) {
     v = dpp_add<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
     v = dpp_add<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
@@ -632,17 +655,8 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                         // lane's total weight and its register-bit half sums,
                         // each squared once; wave sums go to the wave's LDS
                         // row (pacc / nacc), one row per wave.
-                        double tot = 0.0, half[R];
-#pragma unroll
-                        for (int b = 0; b < R; ++b) half[b] = 0.0;
-#pragma unroll
-                        for (int j = 0; j < (1 << R); ++j) {
-                            const double w = double(v[j].x) * double(v[j].x) + double(v[j].y) * double(v[j].y);
-                            tot += w;
-#pragma unroll
-                            for (int b = 0; b < R; ++b)
-                                if ((j >> b) & 1) half[b] += w;
-                        }
+                        double tot, half[R];
+                        reg_half_sums<R>(v, tot, half);
                         const bool last = (tid & 63) == 63;
                         while (o < o1 && ops[o].code == kOpMeas) {
                             const int aux = ops[o].aux;
