@@ -206,9 +206,14 @@ def run_ensemble(spq, torch, L=7, steps=100, dt=0.05, draws=256):
             "bound_std_one_state": 2.0 * 2.0 ** (-(M - 1) / 2)}
 
 
-def measured_traffic(prec_key):
-    """HBM bytes per pass-kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def shape_key(prec_name, info):
+    return "%s_k%d_r%d_c%d" % (prec_name, info["tile_bits"], info["reg_bits"], info["coalesce_bits"])
+
+
+def measured_traffic(key):
+    """HBM bytes per pass-kernel launch of launch shape `key` (shape_key) from
+    the committed rocprofv3 counter summary, or None when that shape was not
+    measured or the kernel source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_pass_ladder2x15_M30_traffic.json")
     src = os.path.join(ROOT, "paper_0710_3747_amd", "csrc")
@@ -219,7 +224,7 @@ def measured_traffic(prec_key):
             h.update(open(os.path.join(src, f), "rb").read())
         if h.hexdigest()[:16] != t["kernel_source_sha256_16"]:
             return None
-        return t[prec_key]["traffic_bytes_per_launch"]
+        return t["shapes"][key]["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
 
@@ -403,7 +408,8 @@ def main():
                    "observable": "FP64 P and norm every step"},
         "roofline": {"bound": "hbm", "achieved": s["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": s["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("c64" if res32 is not None else "c128")
+                     "traffic": measured_traffic(shape_key("c64" if res32 is not None else "c128",
+                                                           head["info"]))
                      if args.workload == "ladder_2x15" else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, scaled)",
                      "alg_bytes_per_launch": 2 * 2 ** w["M"] * head_bytes,

@@ -259,7 +259,7 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  * States small enough for one workgroup have a single shape (one trial).
  * A trial of a few steps runs on a short plan whose passes per step differ
  * from a long run's (the plan repeats in blocks of tens of steps), so the
- * candidates within 20% of the fastest trial (at most three) are ranked by
+ * candidates within 20% of the fastest trial (at most five) are ranked by
  * their trial time per pass launch times the passes per step of their plan
  * for a 1000-step run (or trial_steps, if longer); the others keep their
  * trial time per step.

@@ -125,8 +125,9 @@ spin_options to_options(const Tuned& t) {
 // Candidate launch shapes; the first is the library default.
 std::vector<Tuned> candidates(int32_t prec) {
     if (prec == SPIN_C64)
-        return {{14, 5, 5, 0, 0}, {14, 5, 6, 0, 0}, {14, 4, 5, 0, 0}, {13, 5, 5, 0, 0},
-                {13, 4, 5, 0, 0}, {14, 6, 5, 0, 0}, {12, 4, 5, 0, 0}, {14, 5, 5, 1, 0}};
+        return {{14, 5, 5, 0, 0}, {14, 5, 6, 0, 0}, {14, 4, 5, 0, 0}, {14, 4, 4, 0, 0},
+                {14, 5, 4, 0, 0}, {13, 5, 5, 0, 0}, {13, 4, 5, 0, 0}, {14, 6, 5, 0, 0},
+                {12, 4, 5, 0, 0}, {14, 5, 5, 1, 0}};
     return {{13, 4, 4, 0, 0}, {13, 5, 4, 0, 0}, {13, 3, 4, 0, 0}, {12, 4, 4, 0, 0},
             {12, 3, 4, 0, 0}};
 }
@@ -225,7 +226,7 @@ extern "C" int spin_autotune(int32_t prec, int32_t M, const spin_coupling* J, in
             }
             cand[ci].ms_per_step = tr[ci].trial;
         }
-        // 2) the candidates within 20% of the fastest trial (at most three):
+        // 2) the candidates within 20% of the fastest trial (at most five):
         //    time per launch x passes per step of their long-run plan
         //    (host planning only)
         std::vector<int> order;
@@ -234,7 +235,7 @@ extern "C" int spin_autotune(int32_t prec, int32_t M, const spin_coupling* J, in
         std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tr[a].trial < tr[c].trial; });
         int ibest = order.empty() ? -1 : order[0];
         double best_pred = order.empty() ? 0.0 : tr[order[0]].trial;
-        for (size_t n = 0; n < order.size() && n < 3; ++n) {
+        for (size_t n = 0; n < order.size() && n < 5; ++n) {
             const int ci = order[n];
             if (tr[ci].trial > 1.2 * tr[order[0]].trial || tr[ci].per_launch < 0) continue;
             spin_options o = to_options(cand[ci]);

@@ -87,16 +87,23 @@ def test_ladder_2x12_full_run_fp32_vs_fp64_and_sectors():
     assert np.abs(N64 - 1).max() < 1e-10 and np.abs(N32 - 1).max() < 1e-4
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_ladder_2x15_sectors_periodic_plan(prec):
+# the default shape, then the complex64 shapes the autotuner chooses between
+# for the benchmark (tile bits, register bits, coalescing bits)
+LADDER_SHAPES = [(C128, None), (C64, None), (C64, (14, 5, 6)), (C64, (14, 4, 4)), (C64, (14, 5, 4))]
+
+
+@pytest.mark.parametrize("prec,shape", LADDER_SHAPES, ids=[("c64" if p == C64 else "c128") + ("-default" if s is None else "-k%d-r%d-c%d" % s)
+                              for p, s in LADDER_SHAPES])
+def test_ladder_2x15_sectors_periodic_plan(prec, shape):
     """2 x 15 ladder (M = 30, 8 / 16 GiB), 100 steps: long enough for the
     repeating plan the benchmark uses; sectors with <= 2 or >= 28 spins down
     against the oracle."""
     M, J, dt, steps = 30, workloads.ladder(15), 0.05, 100
-    info = spq.spin_describe_plan(prec, M, J, dt, steps, 0)
+    opts = None if shape is None else dict(zip(("tile_bits", "reg_bits", "coalesce_bits"), shape))
+    info = spq.spin_describe_plan(prec, M, J, dt, steps, 0, None if opts is None else spq.Options(**opts))
     assert info["path"] == 2 and info["period_steps"] > 0
-    note("ladder 2x15 sectors", prec)
-    P, N, _, t = gpu_evolve(prec, M, J, dt, steps, 0, seed=5, keep_state=False)
+    note("ladder 2x15 sectors", prec, shape)
+    P, N, _, t = gpu_evolve(prec, M, J, dt, steps, 0, seed=5, opts=opts, keep_state=False)
     sector_check(t, M, J, dt, steps, 5, prec, [0, 1, 2, 28, 29])
     assert abs(P[0] - 1) < TOL_P[prec]
     assert np.abs(N - 1).max() < (1e-10 if prec == C128 else 1e-4)

@@ -115,6 +115,9 @@ TILED = [
     ("no-couplings", 15, [], 0.1, 5, 3, 0, {}),
     ("large-angles", 15, [(0, 1, 3.0, 40.0), (1, 14, 0.0, -35.0), (3, 9, 0.0, 100.0)], 0.1, 6, 0, 0, {}),
     ("duplicate-pairs", 15, workloads.chain(15) + [(0, 1, 0.0, 1.0), (1, 0, 0.0, 0.5)], 0.05, 12, 1, 0, {}),
+    # 128-byte runs (complex64: 16 amplitudes), 512 and 1024 lanes
+    ("ladder20-c4", 20, workloads.ladder(10), 0.05, 30, 0, 0, {"coalesce_bits": 4}),
+    ("ladder20-r4-c4", 20, workloads.ladder(10), 0.05, 30, 0, 0, {"reg_bits": 4, "coalesce_bits": 4}),
 ]
 
 
