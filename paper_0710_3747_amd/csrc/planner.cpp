@@ -950,10 +950,13 @@ StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, in
     // keeps, tie-breaks), so variants differ by 10-20 % in cost.  The number
     // tried grows with the work of the call (amplitude-steps), keeping the
     // planning time small against the run.
+    // A window of 5 steps pays when few low bits are pinned (c = 4 on the
+    // ladders: 6 % fewer passes); it is tried with policy 2 only.
     std::vector<PassParams> vs;
     for (int rotate : {0, 3, 6, 9, 12, 15})
-        for (int window : {3, 4})
+        for (int window : {3, 4, 5})
             for (int policy : {2, 1}) {
+                if (window == 5 && policy != 2) continue;
                 PassParams v = pp;
                 v.window = window;
                 v.low_policy = policy;
