@@ -229,10 +229,11 @@ def measured_traffic(key):
         return None
 
 
-def cpu_baseline(w, n_couplings=None):
-    """The plain C oracle on a bounded sample of the same workload: one
-    Strang step (all couplings, 2K factor applications, 2 observables) of
-    the M = 30 state, complex128, all OpenMP threads."""
+def cpu_baseline(w, n_couplings=None, steps=2):
+    """The plain C oracle on a bounded sample of the same workload: `steps`
+    Strang steps (all couplings, 2K factor applications each, steps + 1
+    observables) of the M = 30 state, complex128, all OpenMP threads
+    (about 10 s on 16 threads)."""
     import numpy as np
     from oracle import cref
     cref.build(force=False)
@@ -240,14 +241,14 @@ def cpu_baseline(w, n_couplings=None):
     psi = cref.init_random_phase(M, w["polarized"], w["seed"])
     J = w["J"] if n_couplings is None else w["J"][:n_couplings]
     t0 = time.perf_counter()
-    cref.trotter_run(psi, M, J, w["dt"], 1, w["observed"])
+    cref.trotter_run(psi, M, J, w["dt"], steps, w["observed"])
     sec = time.perf_counter() - t0
     del psi
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    nfac = 2 * len(J)
+    nfac = 2 * len(J) * steps
     return dict(value=nfac * 2 ** M / sec, unit="amplitude-updates/s", cores=threads, kind="oracle",
-                sample=f"one Strang step ({nfac} factor applications of {len(J)} couplings, "
-                       f"2 observables) of the M={M} complex128 state; {sec:.2f} s",
+                sample=f"{steps} Strang steps ({nfac} factor applications of {len(J)} couplings, "
+                       f"{steps + 1} observables) of the M={M} complex128 state; {sec:.2f} s",
                 seconds=sec)
 
 
