@@ -229,6 +229,17 @@ def measured_traffic(key):
         return None
 
 
+def cpu_model():
+    """Host CPU model name (Linux /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, n_couplings=None, steps=2):
     """The plain C oracle on a bounded sample of the same workload: `steps`
     Strang steps (all couplings, 2K factor applications each, steps + 1
@@ -415,7 +426,11 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, scaled)",
                      "alg_bytes_per_launch": 2 * 2 ** w["M"] * head_bytes,
                      "kernel": "k_pass", "avg_launch_ms": s["avg_pass_ms"],
-                     "launches": s["launches"]},
+                     "launches": s["launches"],
+                     # a state within the 256 MB Infinity Cache streams from
+                     # there, not from HBM
+                     "state_bytes": 2 ** w["M"] * head_bytes,
+                     "cache_resident": 2 ** w["M"] * head_bytes <= 256 * 2 ** 20},
         "passes_per_step": s["passes_per_step"],
         "launch": "hipGraph replay" if args.graph else "stream",
         "plan_seconds": head["plan_s"],
@@ -488,6 +503,7 @@ def main():
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(w)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
         out["cpu_baseline_single_core"] = cpu_single_core(w)
     print(json.dumps(out), flush=True)
 
