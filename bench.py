@@ -336,7 +336,7 @@ def main():
                     help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the state would shard over the top address bits across GPUs; not built).",
               file=sys.stderr)
         sys.exit(2)

@@ -59,7 +59,7 @@ typedef enum {
     SPIN_EINVAL = -1,        /* bad argument (range, null pointer, non-finite value) */
     SPIN_ENOMEM = -2,        /* workspace allocation failed */
     SPIN_EHIP = -3,          /* HIP runtime error (message in spin_last_error) */
-    SPIN_EUNSUPPORTED = -4,  /* valid request this build cannot serve */
+    SPIN_EUNSUPPORTED = -4,  /* valid request the library cannot serve */
     SPIN_ENOTFOUND = -5      /* no autotuned entry for these arguments */
 } spin_status;
 

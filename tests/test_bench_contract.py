@@ -1,0 +1,50 @@
+"""Host-side checks of bench.py's contract (no GPU): the measured HBM
+traffic resolves for every launch shape the autotuner can choose on the
+2 x 15 ladder while the kernel source is unchanged, an unmeasured shape
+reports none, and more than one GPU is refused with a message."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def counters_current():
+    """True while the kernel sources hash to what the committed counter
+    summary was taken with."""
+    import hashlib
+    import json
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_plan.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_0710_3747_amd", "csrc", f), "rb").read())
+    t = json.load(open(os.path.join(ROOT, "profiles", "k_pass_ladder2x15_M30_traffic.json")))
+    return h.hexdigest()[:16] == t["kernel_source_sha256_16"]
+
+
+@pytest.mark.parametrize("prec,k,r,c", [("c64", 14, 5, 4), ("c64", 14, 4, 4), ("c64", 14, 5, 6),
+                                        ("c128", 13, 4, 4)])
+def test_measured_traffic_per_launch_shape(prec, k, r, c):
+    if not counters_current():
+        pytest.skip("kernel source changed since the HBM counters were taken (bench reports null)")
+    key = bench.shape_key(prec, dict(tile_bits=k, reg_bits=r, coalesce_bits=c))
+    t = bench.measured_traffic(key)
+    alg = 2 * 2 ** 30 * (8 if prec == "c64" else 16)
+    assert t is not None, key
+    # one read and one write sweep per launch, within a few per cent
+    assert alg <= t < 1.03 * alg
+
+
+def test_unmeasured_shape_reports_no_traffic():
+    key = bench.shape_key("c64", dict(tile_bits=12, reg_bits=4, coalesce_bits=5))
+    assert bench.measured_traffic(key) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert p.returncode != 0
+    assert "one GPU" in p.stderr
