@@ -131,7 +131,7 @@ typedef struct {
                              (the plain, unfused schedule, kept as a cross-check) */
     int32_t tile_bits;    /* k of the 2^k-amplitude tiles; 0 = autotuned / default */
     int32_t reg_bits;     /* amplitudes per lane = 2^reg_bits; 0 = default */
-    int32_t coalesce_bits;/* low address bits every tile keeps; 0 = default */
+    int32_t coalesce_bits;/* low address bits every tile keeps; 0 = default (4) */
     int32_t engine;       /* 0 = VALU butterflies (default); 1 = each register stage's
                              factors as one dense 32 x 32 complex matrix on FP32 MFMA
                              (complex64, tile_bits 14, reg_bits 5; tiled path only:

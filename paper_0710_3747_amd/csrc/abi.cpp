@@ -173,7 +173,10 @@ Shape choose_shape(int prec, int M, const spin_options* opt) {
     const bool f32 = prec == SPIN_C64;
     int k = f32 ? 14 : 13;
     s.r = f32 ? 5 : 4;
-    s.c = f32 ? 5 : 4;   // 256-byte contiguous runs
+    // 4 low address bits in every tile: 128-byte runs of complex64 (fewer
+    // passes than 256-byte runs, which outweighs the slower sweep on the
+    // ladders), 256-byte runs of complex128
+    s.c = 4;
     if (opt && opt->tile_bits > 0) {
         k = opt->tile_bits;
         s.r = f32 ? (k <= 12 ? 4 : 5) : 4;

@@ -125,8 +125,8 @@ spin_options to_options(const Tuned& t) {
 // Candidate launch shapes; the first is the library default.
 std::vector<Tuned> candidates(int32_t prec) {
     if (prec == SPIN_C64)
-        return {{14, 5, 5, 0, 0}, {14, 5, 6, 0, 0}, {14, 4, 5, 0, 0}, {14, 4, 4, 0, 0},
-                {14, 5, 4, 0, 0}, {13, 5, 5, 0, 0}, {13, 4, 5, 0, 0}, {14, 6, 5, 0, 0},
+        return {{14, 5, 4, 0, 0}, {14, 5, 5, 0, 0}, {14, 5, 6, 0, 0}, {14, 4, 5, 0, 0},
+                {14, 4, 4, 0, 0}, {13, 5, 5, 0, 0}, {13, 4, 5, 0, 0}, {14, 6, 5, 0, 0},
                 {12, 4, 5, 0, 0}, {14, 5, 5, 1, 0}};
     return {{13, 4, 4, 0, 0}, {13, 5, 4, 0, 0}, {13, 3, 4, 0, 0}, {12, 4, 4, 0, 0},
             {12, 3, 4, 0, 0}};

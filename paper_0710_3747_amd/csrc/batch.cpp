@@ -229,7 +229,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             PassParams pp;
             pp.k = K;
             pp.r = R;
-            pp.c = sizeof(T) == 4 ? 5 : 4;
+            pp.c = 4;    // the library's default shape, so a gang runs the single path's plan
             StreamPlan sp = plan_stream(pr.M, Js[p], dt, n_steps, pr.observed_site, true, pp);
             b.pass0 = int(tb.passes.size());
             for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, tb);
