@@ -105,21 +105,31 @@ def run_profile(spq, torch, w, steps, opts=None):
 
 
 def summarize(res, w, steps, prec_bytes):
+    """Throughput and roofline figures of one timed run.
+
+    The algorithmic bytes of one Trotter step are one sweep of the state,
+    2S (read + write of 2^M amplitudes), however many pass launches the
+    plan needs; a launch processes steps / launches of a step, so its
+    algorithmic bytes are 2S * steps / launches and the achieved rate is
+    2S * steps / timed seconds.  The per-launch sweep rate (2S per launch)
+    is reported beside it as frac_per_pass."""
     M, K = w["M"], len(w["J"])
     amp_updates = 2 * K * 2 ** M * steps
     sec = res["ms_total"] / 1e3
     info = res["info"]
     launches = info["launches"]
     state_bytes = 2 ** M * prec_bytes
-    # algorithmic bytes of one pass-kernel launch: read + write of the state
-    alg_bytes = 2 * state_bytes
+    sweep = 2 * state_bytes
     avg_launch_s = sec / launches
-    achieved = alg_bytes / avg_launch_s / 1e9
+    alg_per_launch = sweep * steps / launches
+    achieved = alg_per_launch / avg_launch_s / 1e9
     return dict(value=amp_updates / sec, ms_per_step=res["ms_total"] / steps,
                 passes_per_step=info["passes_per_step"], launches=launches,
                 avg_pass_ms=avg_launch_s * 1e3, achieved_gbs=achieved,
-                hbm_gbs_per_step=launches * alg_bytes / sec / 1e9,
-                one_sweep_frac=(2 * state_bytes * steps / sec / 1e9) / HBM_PEAK_GBS)
+                alg_bytes_per_launch=alg_per_launch, alg_bytes_per_step=sweep,
+                sweep_gbs_per_pass=sweep / avg_launch_s / 1e9,
+                hbm_gbs_per_step=launches * sweep / sec / 1e9,
+                one_sweep_frac=(sweep * steps / sec / 1e9) / HBM_PEAK_GBS)
 
 
 def other_workload(name):
@@ -135,31 +145,80 @@ def other_workload(name):
     raise ValueError(name)
 
 
-def run_batch(spq, torch, reps=2):
-    """256 independent stars (M uniform in 14..20), 500 steps, complex64,
-    one persistent launch (after one untimed call that plans and warms)."""
+# Non-packed FP32 VALU peak of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (one FMA) x 2.4 GHz.  HIP code here is built without packed FP32.
+VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# VALU work of one amplitude update of the XY butterflies: a factor moves the
+# 2^(M-2) anti-aligned pairs with a three-shear rotation of 6 FMAs per pair,
+# i.e. 1.5 FMA = 3 flops per amplitude of the state.
+FLOPS_PER_AMP_UPDATE = 3.0
+
+
+def run_batch(spq, torch, prec=None, reps=2):
+    """256 independent stars (M uniform in 14..20), 500 steps, one
+    persistent launch (after one untimed call that plans and warms).
+    Returns (summary, P of every problem as a host array)."""
+    import numpy as np
     import workloads
+    prec = spq.SPIN_C64 if prec is None else prec
+    dtype = torch.complex64 if prec == spq.SPIN_C64 else torch.complex128
     cfg = workloads.BATCH_STARS
     spec = workloads.star_batch(cfg["n"], cfg["m_lo"], cfg["m_hi"], cfg["size_seed"],
                                 cfg["coupling_seed0"], cfg["state_seed0"])
     steps, dt = cfg["n_steps"], cfg["dt"]
     probs = []
     for p in spec:
-        probs.append(dict(psi=torch.empty(2 ** p["M"], dtype=torch.complex64, device="cuda"),
+        probs.append(dict(psi=torch.empty(2 ** p["M"], dtype=dtype, device="cuda"),
                           M=p["M"], couplings=p["couplings"], observed_site=0, polarized_site=0,
                           seed=p["seed"], P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"),
                           N=None))
-    spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init_random_phase=True)
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
     for _ in range(reps):
-        spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init_random_phase=True)
+        spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    e1.record(stream)
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / reps
+    if spq.spin_batch_status() != 0:
+        raise RuntimeError("batched stars: " + spq.spin_last_error())
+    sec = e0.elapsed_time(e1) / 1e3 / reps
     upd = sum(2 * len(p["couplings"]) * 2 ** p["M"] * steps for p in spec)
-    return {"workload": "batch_256_stars_M14to20", "steps": steps, "seconds": sec,
-            "amplitude_updates_per_s": upd / sec, "problems": len(spec),
-            "amplitude_updates": upd, "state_bytes": sum(8 * 2 ** p["M"] for p in spec)}
+    flops = FLOPS_PER_AMP_UPDATE * upd
+    out = {"workload": "batch_256_stars_M14to20", "state": "complex64" if prec == spq.SPIN_C64
+           else "complex128", "steps": steps, "seconds": sec,
+           "amplitude_updates_per_s": upd / sec, "problems": len(spec),
+           "amplitude_updates": upd,
+           "state_bytes": sum((8 if prec == spq.SPIN_C64 else 16) * 2 ** p["M"] for p in spec)}
+    if prec == spq.SPIN_C64:
+        out["roofline"] = {"bound": "alu", "achieved": flops / sec / 1e12,
+                           "peak": VALU_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": flops / sec / 1e12 / VALU_F32_PEAK_TFLOPS, "traffic": None,
+                           "flops_per_amplitude_update": FLOPS_PER_AMP_UPDATE,
+                           "kernel": "k_batch"}
+    return out, np.stack([p["P"].cpu().numpy() for p in probs])
+
+
+def run_star(spq, torch, steps, warmup):
+    """The all-to-all star M = 28 (378 couplings) in both precisions, at
+    the complex64 shape the autotuner picks for it (k 14, r 5, c 6) and the
+    complex128 default."""
+    import numpy as np
+    w = other_workload("star_28")
+    o = spq.Options(tile_bits=14, reg_bits=5, coalesce_bits=6)
+    r32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup, o)
+    r64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup, None)
+    s32 = summarize(r32, w, steps, 8)
+    s64 = summarize(r64, w, steps, 16)
+    return {"workload": w["name"], "M": w["M"], "couplings": len(w["J"]), "dt": w["dt"],
+            "steps": steps, "value": s32["value"], "unit": "amplitude-updates/s",
+            "ms_per_step": s32["ms_per_step"], "passes_per_step": s32["passes_per_step"],
+            "one_sweep_frac": s32["one_sweep_frac"],
+            "shape": {k: r32["info"][k] for k in ("tile_bits", "reg_bits", "lanes", "coalesce_bits")},
+            "fp64": {"value": s64["value"], "ms_per_step": s64["ms_per_step"],
+                     "passes_per_step": s64["passes_per_step"]},
+            "err_P_fp32_vs_fp64": float(np.abs(r32["P"] - r64["P"]).max())}
 
 
 def run_ensemble(spq, torch, L=7, steps=100, dt=0.05, draws=256):
@@ -182,7 +241,10 @@ def run_ensemble(spq, torch, L=7, steps=100, dt=0.05, draws=256):
         t0 = time.perf_counter()
         spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, Pb.cpu().numpy()
+        sec = time.perf_counter() - t0
+        if spq.spin_batch_status() != 0:
+            raise RuntimeError("ensemble batch: " + spq.spin_last_error())
+        return sec, Pb.cpu().numpy()
 
     t_ens, P_ens = batch(xs, spq.SPIN_INIT_BASIS)
     t_draws, P_draws = batch(list(range(draws)), spq.SPIN_INIT_RANDOM_PHASE)
@@ -332,6 +394,8 @@ def main():
                     help="launch the timed path through a captured hipGraph (captured untimed)")
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="steps of the all-site profile leg (0 = skip)")
+    ap.add_argument("--star-steps", type=int, default=100,
+                    help="steps of the M = 28 star leg, both precisions (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -352,7 +416,7 @@ def main():
         print(json.dumps(run_ensemble(spq, torch)), flush=True)
         return
     if args.workload == "batch_stars":
-        print(json.dumps(run_batch(spq, torch)), flush=True)
+        print(json.dumps(run_batch(spq, torch)[0]), flush=True)
         return
     w = ladder_workload() if args.workload == "ladder_2x15" else other_workload(args.workload)
     steps, warmup = args.steps, args.warmup
@@ -401,6 +465,8 @@ def main():
     head = res32 if res32 is not None else res64
     head_bytes = 8 if res32 is not None else 16
     s = summarize(head, w, steps, head_bytes)
+    traffic = (measured_traffic(shape_key("c64" if res32 is not None else "c128", head["info"]))
+               if args.workload == "ladder_2x15" else None)
     out = {
         "metric": METRIC,
         "value": s["value"],
@@ -420,11 +486,12 @@ def main():
                    "observable": "FP64 P and norm every step"},
         "roofline": {"bound": "hbm", "achieved": s["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": s["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(shape_key("c64" if res32 is not None else "c128",
-                                                           head["info"]))
-                     if args.workload == "ladder_2x15" else None,
+                     "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, scaled)",
-                     "alg_bytes_per_launch": 2 * 2 ** w["M"] * head_bytes,
+                     "traffic_per_step": traffic * s["launches"] / steps if traffic else None,
+                     "alg_bytes_per_launch": s["alg_bytes_per_launch"],
+                     "alg_bytes_per_step": s["alg_bytes_per_step"],
+                     "frac_per_pass": s["sweep_gbs_per_pass"] / HBM_PEAK_GBS,
                      "kernel": "k_pass", "avg_launch_ms": s["avg_pass_ms"],
                      "launches": s["launches"],
                      # a state within the 256 MB Infinity Cache streams from
@@ -444,7 +511,8 @@ def main():
         out["fp64"] = {"value": s64["value"], "ms_per_step": s64["ms_per_step"],
                        "passes_per_step": s64["passes_per_step"],
                        "achieved_gbs": s64["achieved_gbs"],
-                       "frac": s64["achieved_gbs"] / HBM_PEAK_GBS}
+                       "frac": s64["achieved_gbs"] / HBM_PEAK_GBS,
+                       "frac_per_pass": s64["sweep_gbs_per_pass"] / HBM_PEAK_GBS}
         out["fp32_speedup_vs_fp64"] = s["value"] / s64["value"]
         out["err_P_fp32_vs_fp64"] = float(np.abs(res32["P"] - res64["P"]).max())
         out["norm_drift_fp32"] = float(np.abs(res32["N"] - 1).max())
@@ -457,6 +525,7 @@ def main():
         cp = copy_probe(torch)
         out["roofline"]["copy_GBs"] = cp["copy_GBs"]
         out["roofline"]["frac_of_copy"] = s["achieved_gbs"] / cp["copy_GBs"]
+        out["roofline"]["frac_of_copy_per_pass"] = s["sweep_gbs_per_pass"] / cp["copy_GBs"]
     if args.workload == "ladder_2x15" and res32 is not None and args.engine_steps > 0:
         # stage arithmetic on FP32 MFMA (each stage's factors as one dense
         # 32 x 32 complex matrix) against the VALU butterflies, same shape
@@ -474,6 +543,10 @@ def main():
         if res64 is not None:
             cmp["max_dP_mfma_vs_fp64"] = float(np.abs(rm["P"] - res64["P"][: n + 1]).max())
         out["engine_comparison"] = cmp
+    if args.workload == "ladder_2x15" and res32 is not None and args.star_steps > 0:
+        n = min(args.star_steps, steps)
+        print(f"[bench] star M=28, {n} steps", file=sys.stderr, flush=True)
+        out["star_28"] = run_star(spq, torch, n, 2)
     if args.workload == "ladder_2x15" and res32 is not None and args.profile_steps > 0:
         # every site's polarisation after every step, in the same passes
         import numpy as np
@@ -495,8 +568,14 @@ def main():
     if args.workload != "ladder_2x15":
         out["metric"] = "amplitude-updates/s per Trotter step (secondary workload)"
     elif not args.no_batch:
+        import numpy as np
         print("[bench] batched stars", file=sys.stderr, flush=True)
-        out["batch_stars"] = run_batch(spq, torch)
+        bs, P32 = run_batch(spq, torch)
+        print("[bench] batched stars, complex128", file=sys.stderr, flush=True)
+        bs64, P64 = run_batch(spq, torch, spq.SPIN_C128, reps=1)
+        bs["fp64"] = {k: bs64[k] for k in ("seconds", "amplitude_updates_per_s", "state_bytes")}
+        bs["err_P_fp32_vs_fp64"] = float(np.abs(P32 - P64).max())
+        out["batch_stars"] = bs
         print("[bench] basis-state ensemble vs random phase", file=sys.stderr, flush=True)
         out["ensemble_vs_random_phase"] = run_ensemble(spq, torch)
     if not args.no_cpu_baseline:

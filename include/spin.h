@@ -178,13 +178,22 @@ int spin_trotter_evolve_profile(void *psi, int32_t prec, int32_t M, const spin_c
                                 double *N_dev, const spin_options *opt, void *stream);
 
 /*
- * spin_local_polarization -- P = sum_x (1 - 2 bit_site(x)) |psi_x|^2 and the
- * norm, FP64, of the state as it is (Eq. (2), P = 2(W - 1/2)).
- *   out_dev : device FP64 array of 2 entries: out_dev[0] = P, out_dev[1] = N.
- * Errors: SPIN_EINVAL (null pointers, prec, M, site), SPIN_ENOMEM, SPIN_EHIP.
+ * spin_local_polarization -- P = sum_x (1 - 2 bit_site(x)) |psi_x|^2, FP64,
+ * of the state as it is (Eq. (2), P = 2(W - 1/2); not divided by the norm).
+ *   psi   : device state, 2^M amplitudes of `prec` (read only).
+ *   site  : 0 <= site < M.
+ *   P_dev : device FP64 array of 1 entry, receives P.
+ * Errors: SPIN_EINVAL (null psi/P_dev, prec, M, site), SPIN_ENOMEM, SPIN_EHIP.
  */
 int spin_local_polarization(const void *psi, int32_t prec, int32_t M, int32_t site,
-                            double *out_dev, void *stream);
+                            double *P_dev, void *stream);
+
+/*
+ * spin_local_polarization_ex -- as spin_local_polarization, and the norm
+ * N = sum_x |psi_x|^2 (FP64) into N_dev[0] when N_dev is not NULL.
+ */
+int spin_local_polarization_ex(const void *psi, int32_t prec, int32_t M, int32_t site,
+                               double *P_dev, double *N_dev, void *stream);
 
 /*
  * Batched evolution of independent problems of uneven size (disorder
@@ -218,14 +227,29 @@ enum {
  * initial state (`init`, one of SPIN_INIT_*), then evolve it n_steps steps
  * (as spin_trotter_evolve) writing its P and N.
  *   probs, n       : host array of n >= 0 problems (read during the call).
- *   J_all, K_total : host array holding every problem's couplings.
- * The states must not overlap.  The call synchronises `stream`.  Errors as
- * spin_trotter_evolve (plus SPIN_EINVAL for a bad init or a basis index
- * >= 2^M), reported for the first offending problem.
+ *   J_all, K_total : host array holding every problem's couplings; K_total
+ *                    bounds each problem's [coupling_offset, +K) range.
+ *   init           : SPIN_INIT_* (one initial state for every problem).
+ * The states must not overlap.  The work is enqueued on `stream` and the
+ * call returns without synchronising (the first call with a new problem set
+ * plans and uploads its tables synchronously; later equal calls reuse them
+ * until spin_release_caches).  Problems larger than one workgroup's tile run
+ * as gangs of workgroups that meet at bounded device-wide barriers; if a
+ * barrier times out, the problem's P is set to NaN and spin_batch_status
+ * reports it.  Errors as spin_trotter_evolve (plus SPIN_EINVAL for a bad
+ * init or a basis index >= 2^M), reported for the first offending problem.
  */
 int spin_trotter_evolve_batch(const spin_problem *probs, int32_t n, const spin_coupling *J_all,
                               int64_t K_total, int32_t prec, double dt, int64_t n_steps,
                               int32_t init, void *stream);
+
+/*
+ * spin_batch_status -- synchronises `stream`, then reports whether any
+ * batched launch on the current device that has completed timed out at a
+ * gang barrier since the previous query (SPIN_EHIP with a message) or not
+ * (SPIN_OK), and clears that status.
+ */
+int spin_batch_status(void *stream);
 
 /*
  * spin_prepare_plan -- plans the call spin_trotter_evolve_ex would make with
@@ -244,8 +268,9 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K
  * Autotuner (for callers that run the same problem many times, e.g. long or
  * repeated evolutions).  spin_autotune times trial evolutions of
  * `trial_steps` steps for a set of launch shapes of the tiled path (tile
- * bits, register bits, lanes, coalescing bits; complex64 also the MFMA
- * matrix engine) and keeps the fastest:
+ * bits, register bits, lanes, coalescing bits; VALU butterflies -- the MFMA
+ * matrix engine is selectable through spin_options only) and keeps the
+ * fastest:
  *   - key: device architecture and CU count, prec, M, observed_site, dt and
  *     the coupling list (order and values);
  *   - the trials run on a scratch state the call allocates (2^M amplitudes)

@@ -20,7 +20,8 @@ __all__ = [
     "SPIN_C64", "SPIN_C128", "SpinError", "library_path", "load_library",
     "spin_init_random_phase", "spin_init_product", "spin_trotter_evolve", "spin_trotter_evolve_ex",
     "spin_trotter_evolve_profile", "SPIN_ALL_SITES",
-    "spin_local_polarization", "spin_trotter_evolve_batch", "spin_describe_plan",
+    "spin_local_polarization", "spin_local_polarization_ex", "spin_trotter_evolve_batch",
+    "spin_batch_status", "spin_describe_plan",
     "spin_plan_trace", "spin_last_error", "spin_release_caches", "spin_version",
     "Options", "Problem",
 ]
@@ -103,6 +104,8 @@ def load_library():
     lib.spin_trotter_evolve_ex.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, op, vp]
     lib.spin_trotter_evolve_profile.argtypes = [vp, i32, i32, cp, i32, dbl, i64, vp, vp, op, vp]
     lib.spin_local_polarization.argtypes = [vp, i32, i32, i32, vp, vp]
+    lib.spin_local_polarization_ex.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+    lib.spin_batch_status.argtypes = [vp]
     lib.spin_trotter_evolve_batch.argtypes = [ctypes.POINTER(Problem), i32, cp, i64, i32, dbl,
                                               i64, i32, vp]
     lib.spin_prepare_plan.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op]
@@ -120,7 +123,8 @@ def load_library():
     for name in ("spin_init_random_phase", "spin_init_product", "spin_trotter_evolve",
                  "spin_trotter_evolve_ex",
                  "spin_trotter_evolve_profile",
-                 "spin_local_polarization", "spin_trotter_evolve_batch", "spin_prepare_plan",
+                 "spin_local_polarization", "spin_local_polarization_ex",
+                 "spin_trotter_evolve_batch", "spin_batch_status", "spin_prepare_plan",
                  "spin_describe_plan", "spin_plan_trace", "spin_autotune", "spin_tuned_options"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -231,17 +235,33 @@ def spin_trotter_evolve_profile(psi, M: int, couplings, dt: float, n_steps: int,
                                            _stream(stream)))
 
 
-def spin_local_polarization(psi, M: int, site: int, out, stream=None) -> None:
-    """out[0] = P, out[1] = N of the state as it is (FP64 device tensor)."""
+def spin_local_polarization(psi, M: int, site: int, P, stream=None) -> None:
+    """P[0] = polarisation of ``site`` in the state as it is (FP64 device tensor)."""
     lib = load_library()
     p, prec = _state(psi, M)
-    _check(lib.spin_local_polarization(p, prec, M, site, _f64(out, 2, "out"), _stream(stream)))
+    _check(lib.spin_local_polarization(p, prec, M, site, _f64(P, 1, "P"), _stream(stream)))
+
+
+def spin_local_polarization_ex(psi, M: int, site: int, P, N=None, stream=None) -> None:
+    """P[0] = polarisation of ``site``, N[0] = norm (if N is given)."""
+    lib = load_library()
+    p, prec = _state(psi, M)
+    _check(lib.spin_local_polarization_ex(p, prec, M, site, _f64(P, 1, "P"), _f64(N, 1, "N"),
+                                          _stream(stream)))
+
+
+def spin_batch_status(stream=None) -> int:
+    """Synchronises the stream; 0 if no batched launch timed out at a gang
+    barrier since the last query, else the error status (message in
+    spin_last_error())."""
+    return int(load_library().spin_batch_status(_stream(stream)))
 
 
 def spin_trotter_evolve_batch(problems: Sequence[dict], prec: int, dt: float, n_steps: int,
                               init_random_phase: bool = True, stream=None,
                               init: Optional[int] = None) -> None:
-    """Evolves independent problems in one launch.
+    """Evolves independent problems in one launch (asynchronous on the
+    stream; spin_batch_status() reports gang-barrier time-outs).
 
     Each problem is a dict with keys psi (device tensor), M, couplings,
     observed_site, P, optional N, polarized_site and seed.  `init` (one of

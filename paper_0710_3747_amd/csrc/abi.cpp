@@ -599,12 +599,12 @@ int spin_init_product(void* psi, int32_t prec, int32_t M, int32_t polarized_site
     return SPIN_OK;
 }
 
-int spin_local_polarization(const void* psi, int32_t prec, int32_t M, int32_t site,
-                            double* out_dev, void* stream) {
+int spin_local_polarization_ex(const void* psi, int32_t prec, int32_t M, int32_t site,
+                               double* P_dev, double* N_dev, void* stream) {
     int rc = validate_common(psi, prec, M);
     if (rc) return rc;
     if (site < 0 || site >= M) return fail(SPIN_EINVAL, "site out of range");
-    if (!out_dev) return fail(SPIN_EINVAL, "out_dev is NULL");
+    if (!P_dev) return fail(SPIN_EINVAL, "P_dev is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nblk = 1024;
     void* scratch = nullptr;
@@ -612,10 +612,15 @@ int spin_local_polarization(const void* psi, int32_t prec, int32_t M, int32_t si
     double* part = static_cast<double*>(scratch);
     hipError_t e = prec == SPIN_C64 ? launch_observe<float>(psi, M, site, part, nblk, st)
                                     : launch_observe<double>(psi, M, site, part, nblk, st);
-    if (e == hipSuccess) e = launch_reduce(part, nblk, 1, 0, 1, out_dev, out_dev + 1, st);
+    if (e == hipSuccess) e = launch_reduce(part, nblk, 1, 0, 1, P_dev, N_dev, st);
     if (e != hipSuccess) return fail(SPIN_EHIP, std::string("observe launch: ") + hipGetErrorString(e));
     g_err.clear();
     return SPIN_OK;
+}
+
+int spin_local_polarization(const void* psi, int32_t prec, int32_t M, int32_t site, double* P_dev,
+                            void* stream) {
+    return spin_local_polarization_ex(psi, prec, M, site, P_dev, nullptr, stream);
 }
 
 }  // extern "C"

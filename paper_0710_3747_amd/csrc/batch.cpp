@@ -17,9 +17,33 @@
 
 namespace spinqp {
 
+// Device tables of the grouped one-workgroup launches of one batch call,
+// kept (like the persistent launch's) until spin_release_caches so the call
+// can return without waiting for the launches.
+struct ResidentBatch {
+    struct Group {
+        int r = 0, nt = 0, njobs = 0;
+        void *d_jobs = nullptr, *d_st = nullptr, *d_ops = nullptr;
+    };
+    std::vector<Group> groups;
+    ~ResidentBatch() {
+        for (Group& g : groups)
+            for (void* p : {g.d_jobs, g.d_st, g.d_ops})
+                if (p) (void)hipFree(p);
+    }
+};
+
+static std::mutex g_rmu;
+static std::map<std::vector<double>, std::shared_ptr<ResidentBatch>> g_rcache;
+
+static std::vector<double> batch_key(const spin_problem* probs, int n,
+                                     const std::vector<std::vector<Coupling>>& Js, int prec,
+                                     double dt, int64_t n_steps, int init, int dev);
+
 template <typename T>
-static int batch_resident(const spin_problem* probs, int32_t n, const std::vector<std::vector<Coupling>>& Js,
-                          double dt, int64_t n_steps, int init, hipStream_t st) {
+static int batch_resident_build(const spin_problem* probs, int32_t n,
+                                const std::vector<std::vector<Coupling>>& Js, double dt, int init,
+                                ResidentBatch* rb) {
     // group problems by kernel shape; each group is one launch with one
     // workgroup per problem, largest states first
     const int rmax = sizeof(T) == 4 ? 5 : 4;
@@ -75,36 +99,54 @@ static int batch_resident(const spin_problem* probs, int32_t n, const std::vecto
             shared[skey] = j;
             jobs.push_back(j);
         }
-        // tables live until the launch has run: allocate, copy, launch, free
-        // after synchronising the stream (batch calls are not on hot loops)
-        void *d_jobs = nullptr, *d_st = nullptr, *d_ops = nullptr;
-        auto cleanup = [&]() {
-            if (d_jobs) (void)hipFree(d_jobs);
-            if (d_st) (void)hipFree(d_st);
-            if (d_ops) (void)hipFree(d_ops);
+        ResidentBatch::Group gr;
+        gr.r = g.first.first;
+        gr.nt = g.first.second;
+        gr.njobs = int(jobs.size());
+        rb->groups.push_back(gr);
+        ResidentBatch::Group& G = rb->groups.back();
+        auto up = [&](const void* src, size_t bytes, void** dst) -> int {
+            if (bytes == 0) bytes = 16;
+            if (hipMalloc(dst, bytes) != hipSuccess) return fail(SPIN_ENOMEM, "batch table allocation failed");
+            if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+                return fail(SPIN_EHIP, "batch table upload failed");
+            return SPIN_OK;
         };
-        if (hipMalloc(&d_jobs, jobs.size() * sizeof(ResidentJob)) != hipSuccess ||
-            hipMalloc(&d_st, std::max<size_t>(16, tb.stages.size() * sizeof(DevStage))) != hipSuccess ||
-            hipMalloc(&d_ops, std::max<size_t>(16, tb.ops.size() * sizeof(DevOp<T>))) != hipSuccess) {
-            cleanup();
-            return fail(SPIN_ENOMEM, "batch table allocation failed");
-        }
-        hipError_t e = hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(ResidentJob),
-                                      hipMemcpyHostToDevice, st);
-        if (e == hipSuccess && !tb.stages.empty())
-            e = hipMemcpyAsync(d_st, tb.stages.data(), tb.stages.size() * sizeof(DevStage),
-                               hipMemcpyHostToDevice, st);
-        if (e == hipSuccess && !tb.ops.empty())
-            e = hipMemcpyAsync(d_ops, tb.ops.data(), tb.ops.size() * sizeof(DevOp<T>),
-                               hipMemcpyHostToDevice, st);
-        ResidentJob none{};
-        if (e == hipSuccess)
-            e = launch_resident<T>(g.first.first, g.first.second, none,
-                                   static_cast<const ResidentJob*>(d_jobs), int(jobs.size()),
-                                   static_cast<const DevStage*>(d_st),
-                                   static_cast<const DevOp<T>*>(d_ops), n_steps, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        cleanup();
+        int rc;
+        if ((rc = up(jobs.data(), jobs.size() * sizeof(ResidentJob), &G.d_jobs))) return rc;
+        if ((rc = up(tb.stages.empty() ? nullptr : tb.stages.data(), tb.stages.size() * sizeof(DevStage),
+                     &G.d_st)))
+            return rc;
+        if ((rc = up(tb.ops.empty() ? nullptr : tb.ops.data(), tb.ops.size() * sizeof(DevOp<T>), &G.d_ops)))
+            return rc;
+    }
+    return SPIN_OK;
+}
+
+template <typename T>
+static int batch_resident(const spin_problem* probs, int32_t n, const std::vector<std::vector<Coupling>>& Js,
+                          int prec, double dt, int64_t n_steps, int init, hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SPIN_EHIP, "hipGetDevice failed");
+    const std::vector<double> key = batch_key(probs, n, Js, prec, dt, n_steps, init, dev);
+    std::shared_ptr<ResidentBatch> rb;
+    {
+        std::lock_guard<std::mutex> lk(g_rmu);
+        auto it = g_rcache.find(key);
+        if (it != g_rcache.end()) rb = it->second;
+    }
+    if (!rb) {
+        rb = std::make_shared<ResidentBatch>();
+        const int rc = batch_resident_build<T>(probs, n, Js, dt, init, rb.get());
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lk(g_rmu);
+        g_rcache[key] = rb;
+    }
+    ResidentJob none{};
+    for (const ResidentBatch::Group& G : rb->groups) {
+        const hipError_t e = launch_resident<T>(G.r, G.nt, none, static_cast<const ResidentJob*>(G.d_jobs),
+                                                G.njobs, static_cast<const DevStage*>(G.d_st),
+                                                static_cast<const DevOp<T>*>(G.d_ops), n_steps, st);
         if (e != hipSuccess) return fail(SPIN_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
     return SPIN_OK;
@@ -132,10 +174,37 @@ struct BatchCache {
 
 static std::mutex g_bmu;
 static std::map<std::vector<double>, std::shared_ptr<BatchCache>> g_bcache;
+// Per device: sticky status word of the persistent launches (non-zero once a
+// gang barrier has timed out), read and cleared by spin_batch_status.
+static std::map<int, int*> g_status;
+
+static int status_word(int dev, int** out) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    int*& w = g_status[dev];
+    if (!w) {
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(int)) != hipSuccess) return fail(SPIN_ENOMEM, "status word allocation failed");
+        const int zero = 0;
+        if (hipMemcpy(p, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(p);
+            return fail(SPIN_EHIP, "status word initialisation failed");
+        }
+        w = static_cast<int*>(p);
+    }
+    *out = w;
+    return SPIN_OK;
+}
 
 void release_batch_caches() {
-    std::lock_guard<std::mutex> lk(g_bmu);
-    g_bcache.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        g_bcache.clear();
+        for (auto& kv : g_status)
+            if (kv.second) (void)hipFree(kv.second);
+        g_status.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_rmu);
+    g_rcache.clear();
 }
 
 // Key: everything the tables and the launch depend on.
@@ -229,7 +298,9 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             PassParams pp;
             pp.k = K;
             pp.r = R;
-            pp.c = 4;    // the library's default shape, so a gang runs the single path's plan
+            // the library's default launch shape; a gang plans one scheduling
+            // variant (plan_stream), not the single path's variant search
+            pp.c = 4;
             StreamPlan sp = plan_stream(pr.M, Js[p], dt, n_steps, pr.observed_site, true, pp);
             b.pass0 = int(tb.passes.size());
             for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, tb);
@@ -351,6 +422,8 @@ static int batch_persistent(const spin_problem* probs, const std::vector<int>& s
         std::lock_guard<std::mutex> lk(g_bmu);
         g_bcache[key] = bc;
     }
+    int* status = nullptr;
+    if (int rc = status_word(dev, &status)) return rc;
     auto enqueue = [&](hipStream_t s) {
         return launch_batch<T>(bc->nslots, static_cast<const BatchProblem*>(bc->d_probs),
                                static_cast<const BatchJob*>(bc->d_jobs),
@@ -360,7 +433,7 @@ static int batch_persistent(const spin_problem* probs, const std::vector<int>& s
                                static_cast<const DevOp<T>*>(bc->d_ops),
                                static_cast<const int2*>(bc->d_launch),
                                static_cast<double*>(bc->d_part), static_cast<int*>(bc->d_ctr),
-                               bc->ncounters, static_cast<int*>(bc->d_err), n_steps, s);
+                               bc->ncounters, static_cast<int*>(bc->d_err), status, n_steps, s);
     };
     hipError_t e = hipSuccess;
     if (use_graph) {
@@ -385,17 +458,11 @@ static int batch_persistent(const spin_problem* probs, const std::vector<int>& s
         if (e == hipSuccess) e = hipGraphLaunch(bc->exec, bc->side);
         if (e == hipSuccess) e = hipEventRecord(ev, bc->side);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
-        if (e == hipSuccess) e = hipStreamSynchronize(bc->side);
         (void)hipEventDestroy(ev);
     } else {
         e = enqueue(st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
     if (e != hipSuccess) return fail(SPIN_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
-    int err = 0;
-    if ((e = hipMemcpy(&err, bc->d_err, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
-        return fail(SPIN_EHIP, std::string("batch status: ") + hipGetErrorString(e));
-    if (err) return fail(SPIN_EHIP, "batch: a gang barrier timed out (workgroups not co-resident?)");
     return SPIN_OK;
 }
 
@@ -452,8 +519,8 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
                 sp.push_back(probs[p]);
                 sj.push_back(Js[p]);
             }
-            rc = prec == SPIN_C64 ? batch_resident<float>(sp.data(), int(sp.size()), sj, dt, n_steps, init, st)
-                                  : batch_resident<double>(sp.data(), int(sp.size()), sj, dt, n_steps, init, st);
+            rc = prec == SPIN_C64 ? batch_resident<float>(sp.data(), int(sp.size()), sj, prec, dt, n_steps, init, st)
+                                  : batch_resident<double>(sp.data(), int(sp.size()), sj, prec, dt, n_steps, init, st);
             if (rc) return rc;
         }
         if (!big.empty()) {
@@ -463,6 +530,37 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
         }
         if (rc == SPIN_OK) fail(SPIN_OK, "");
         return rc;
+    } catch (const std::exception& e) {
+        return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());
+    }
+}
+
+extern "C" int spin_batch_status(void* stream) {
+    try {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return fail(SPIN_EHIP, std::string("batch status: ") + hipGetErrorString(e));
+        int* w = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_bmu);
+            auto it = g_status.find(dev);
+            if (it != g_status.end()) w = it->second;
+        }
+        if (!w) {
+            fail(SPIN_OK, "");
+            return SPIN_OK;      // no persistent launch on this device yet
+        }
+        int v = 0;
+        const int zero = 0;
+        e = hipMemcpy(&v, w, sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && v != 0) e = hipMemcpy(w, &zero, sizeof(int), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(SPIN_EHIP, std::string("batch status: ") + hipGetErrorString(e));
+        if (v != 0)
+            return fail(SPIN_EHIP, "batch: a gang barrier timed out (workgroups not co-resident?); "
+                                   "the affected problems' P were set to NaN");
+        fail(SPIN_OK, "");
+        return SPIN_OK;
     } catch (const std::exception& e) {
         return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());
     }

@@ -1031,6 +1031,11 @@ __global__ void k_fill_int(int* p, int n, int v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Folds a launch's error flag into the device's sticky batch status word.
+__global__ void k_status_or(const int* err, int* status) {
+    if (threadIdx.x == 0 && *err != 0) atomicOr(status, *err);
+}
+
 // ------------------------------------------------------------- launchers
 static inline int grid_for(uint64_t n, int per_block, int cap) {
     uint64_t g = (n + per_block - 1) / per_block;
@@ -1185,7 +1190,7 @@ template <typename T>
 hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* jobs,
                         const int* job_start, const DevPass* passes, const DevStage* stages,
                         const DevOp<T>* ops, const int2* launches, double* partials, int* counters,
-                        int ncounters, int* err, int64_t n_steps, hipStream_t st) {
+                        int ncounters, int* err, int* status, int64_t n_steps, hipStream_t st) {
     // counters and the error flag start at zero (a fill kernel, not a
     // memset node, so the pair can sit in a captured graph)
     hipLaunchKernelGGL(k_fill_int, dim3(64), dim3(256), 0, st, counters, ncounters, 0);
@@ -1198,15 +1203,17 @@ hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* j
         hipLaunchKernelGGL((k_batch<T, 4, 512>), dim3(nslots), dim3(512), 0, st, probs, jobs,
                            job_start, passes, stages, ops, launches, partials, counters, err,
                            n_steps);
+    hipLaunchKernelGGL(k_status_or, dim3(1), dim3(64), 0, st, err, status);
     return hipGetLastError();
 }
 
 template hipError_t launch_batch<float>(int, const BatchProblem*, const BatchJob*, const int*,
                                         const DevPass*, const DevStage*, const DevOp<float>*,
-                                        const int2*, double*, int*, int, int*, int64_t, hipStream_t);
+                                        const int2*, double*, int*, int, int*, int*, int64_t,
+                                        hipStream_t);
 template hipError_t launch_batch<double>(int, const BatchProblem*, const BatchJob*, const int*,
                                          const DevPass*, const DevStage*, const DevOp<double>*,
-                                         const int2*, double*, int*, int, int*, int64_t,
+                                         const int2*, double*, int*, int, int*, int*, int64_t,
                                          hipStream_t);
 template hipError_t launch_init<float>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_init<double>(void*, int, int, uint64_t, hipStream_t);

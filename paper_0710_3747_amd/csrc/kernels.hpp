@@ -69,12 +69,13 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
                        const DevStage* stages, const DevOp<T>* ops, int pass_index,
                        int64_t tiles_per_wg, int nwg, double* partials, int64_t step_offset,
                        int ch, hipStream_t st);
-// Persistent batch launch over `nslots` workgroups (all resident at once).
+// Persistent batch launch over `nslots` workgroups (all resident at once);
+// a gang-barrier time-out sets `err` and is or-ed into `*status`.
 template <typename T>
 hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* jobs,
                         const int* job_start, const DevPass* passes, const DevStage* stages,
                         const DevOp<T>* ops, const int2* launches, double* partials, int* counters,
-                        int ncounters, int* err, int64_t n_steps, hipStream_t st);
+                        int ncounters, int* err, int* status, int64_t n_steps, hipStream_t st);
 int batch_tile_bits(bool f32);
 
 template <typename T>

@@ -77,15 +77,48 @@ def test_local_polarization(prec):
     rng = np.random.default_rng(0)
     psi0 = psi0 + 1e-3 * (rng.standard_normal(2 ** M) + 1j * rng.standard_normal(2 ** M))
     psi = gpu_state(prec, M, psi0=psi0)
-    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    # guard entries after the outputs: the calls write exactly one value each
+    out = torch.full((4,), 7.0, dtype=torch.float64, device="cuda")
     for site in (0, 4, 16):
         note("observe", prec, site)
-        spq.spin_local_polarization(psi, M, site, out)
+        spq.spin_local_polarization(psi, M, site, out[0:1])
+        spq.spin_local_polarization_ex(psi, M, site, out[1:2], out[2:3])
         torch.cuda.synchronize()
         ref_state = psi.cpu().numpy().astype(np.complex128)
-        P, N = out.cpu().numpy()
+        P, P2, N, guard = out.cpu().numpy()
         assert abs(P - oracle.local_polarization(ref_state, M, site)) < 1e-12
+        assert P2 == P and guard == 7.0
         assert abs(N - oracle.norm2(ref_state)) < 1e-12
+        spq.spin_local_polarization_ex(psi, M, site, out[3:4], None)
+        torch.cuda.synchronize()
+        assert float(out[3]) == P
+        out[3] = 7.0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M", [10, 16])
+def test_nan_written_from_the_host_shows_in_P_and_N(prec, M):
+    """Failure detection: a NaN put into one amplitude of the state on the
+    host (then copied to the device) shows up in P[k] and N[k] of every
+    step, in spin_local_polarization and in a batched run -- the
+    one-workgroup path (M = 10) and the tiled path (M = 16)."""
+    import torch
+    J = workloads.ladder(M // 2)
+    psi0 = oracle.random_phase_state(M, 0, 3)
+    psi0[2 * 77] = complex(float("nan"), 0.0)
+    note("nan injection", prec, M)
+    P, N, _, t = gpu_evolve(prec, M, J, 0.05, 6, 0, psi0=psi0, keep_state=False)
+    assert np.isnan(P).all() and np.isnan(N).all()
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    spq.spin_local_polarization_ex(t, M, 0, out[0:1], out[1:2])
+    torch.cuda.synchronize()
+    assert np.isnan(out.cpu().numpy()).all()
+    Pb = torch.zeros(7, dtype=torch.float64, device="cuda")
+    psib = torch.from_numpy(psi0).to(torch_dtype(prec)).cuda()
+    spq.spin_trotter_evolve_batch([dict(psi=psib, M=M, couplings=J, observed_site=0, P=Pb)], prec,
+                                  0.05, 6, init_random_phase=False)
+    assert spq.spin_batch_status() == 0
+    assert np.isnan(Pb.cpu().numpy()).all()
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -224,6 +257,7 @@ def test_batch_matches_single_runs(prec):
                           N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
     note("batch", prec, [p["M"] for p in probs])
     spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for p in probs:
         P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
@@ -252,6 +286,7 @@ def test_batch_gangs_match_single_runs(prec):
                           N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
     note("batch gangs", prec, Ms)
     spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for p in probs:
         P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
@@ -262,6 +297,7 @@ def test_batch_gangs_match_single_runs(prec):
     assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
     # a second call with the same problems reuses the cached launch
     spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     assert np.abs(probs[0]["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
 
@@ -282,6 +318,7 @@ def test_batch_config_256_uneven_stars():
                           N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
     note("batch 256 stars")
     spq.spin_trotter_evolve_batch(probs, C64, dt, steps, init_random_phase=True)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for p in probs:
         P, N = p["P"].cpu().numpy(), p["N"].cpu().numpy()
@@ -298,6 +335,54 @@ def test_batch_config_256_uneven_stars():
     p = probs[picks[0]]     # the oracle on a smallest problem, full run
     Pw, _, _ = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
     assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[C64]
+
+
+_BATCH_ORACLE = {}
+
+
+def _batch_subset(spec):
+    """A seeded subset of the 256-star batch: one problem of each size
+    15..19 and two of size 20 (the gangs of 2..32 workgroups)."""
+    rng = np.random.default_rng(20)
+    out = []
+    for M, n in ((15, 1), (16, 1), (17, 1), (18, 1), (19, 1), (20, 2)):
+        idx = [i for i, p in enumerate(spec) if p["M"] == M]
+        out += [int(i) for i in rng.choice(idx, size=n, replace=False)]
+    return out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [C64, C128], ids=["c64", "c128"])
+def test_batch_config_256_gang_problems_match_oracle(prec):
+    """256 stars (M uniform in 14..20), 500 steps at dt = 0.02, one
+    persistent launch in each precision: a seeded subset of the problems run
+    by gangs (one of each size 15..19, two of size 20) against the oracle's
+    loop over all 500 steps -- every P[k], N[k] and the final state; the
+    phase-draw mean of Eq. (4) averages such problems."""
+    import torch
+    cfg = workloads.BATCH_STARS
+    spec = workloads.star_batch(cfg["n"], cfg["m_lo"], cfg["m_hi"], cfg["size_seed"],
+                                cfg["coupling_seed0"], cfg["state_seed0"])
+    steps, dt = cfg["n_steps"], cfg["dt"]
+    probs = []
+    for p in spec:
+        probs.append(dict(psi=torch.empty(2 ** p["M"], dtype=torch_dtype(prec), device="cuda"),
+                          M=p["M"], couplings=p["couplings"], observed_site=0, polarized_site=0,
+                          seed=p["seed"], P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"),
+                          N=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
+    note("batch 256 stars vs oracle", prec)
+    spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init_random_phase=True)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
+    for i in _batch_subset(spec):
+        p = probs[i]
+        if i not in _BATCH_ORACLE:
+            note("oracle star", i, "M", p["M"])
+            _BATCH_ORACLE[i] = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+        Pw, Nw, psiw = _BATCH_ORACLE[i]
+        P, N = p["P"].cpu().numpy(), p["N"].cpu().numpy()
+        assert np.abs(P - Pw).max() < TOL_P[prec], (i, p["M"], np.abs(P - Pw).max())
+        assert np.abs(N - Nw).max() < TOL_P[prec], (i, p["M"])
+        assert_state_close(p["psi"].cpu().numpy().astype(np.complex128), psiw, prec)
 
 
 def test_autotune_picks_a_shape_stores_it_and_it_evolves_correctly(tmp_path):
@@ -367,6 +452,7 @@ def test_ensemble_of_basis_states_matches_trotterised_ensemble(prec):
                   observed_site=0, seed=x, P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"))
              for x in xs]
     spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init=spq.SPIN_INIT_BASIS)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     Pbar = torch.stack([p["P"] for p in probs]).mean(0).cpu().numpy()
     want = ed.ensemble_P_trotter(M, J, dt, steps, 0, 0)
@@ -391,6 +477,7 @@ def test_basis_init_on_the_gang_path():
                   observed_site=3, seed=x, P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda"))
              for x in xs]
     spq.spin_trotter_evolve_batch(probs, C128, dt, steps, init=spq.SPIN_INIT_BASIS)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for pr, x in zip(probs, xs):
         psi0 = np.zeros(2 ** M, dtype=np.complex128)
@@ -544,6 +631,7 @@ def test_batch_product_init_matches_single_runs(prec):
         spq.spin_trotter_evolve(ref, M, J, dt, steps, 0, Pr)
         singles.append((ref, Pr))
     spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init=spq.SPIN_INIT_PRODUCT)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for pr, (ref, Pr) in zip(probs, singles):
         assert np.abs(pr["P"].cpu().numpy() - Pr.cpu().numpy()).max() < 2e-5
@@ -586,6 +674,7 @@ def test_fig3a_entangled_vs_product_states_M14():
                           couplings=J, observed_site=0, polarized_site=0, seed=1000 + a,
                           P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
     spq.spin_trotter_evolve_batch(probs, C64, dt, steps, init=spq.SPIN_INIT_PRODUCT)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     mean = np.mean([p["P"].cpu().numpy() for p in probs], axis=0)
     note("fig3a rms mean630", rms(mean))
@@ -607,7 +696,7 @@ def test_graph_replays_equal_eager_runs(prec):
     psi = torch.empty(2 ** M, dtype=torch_dtype(prec), device="cuda")
     P = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
     Pall = torch.zeros((steps + 1) * M, dtype=torch.float64, device="cuda")
-    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
     g = spq.Options(use_graph=1)
     for rep in range(3):
         spq.spin_init_random_phase(psi, M, 0, 6)
@@ -672,6 +761,7 @@ def test_batch_random_graphs_match_oracle(prec):
                           P=torch.zeros(steps + 1, dtype=torch.float64, device="cuda")))
     note("batch random graphs", prec, [p["M"] for p in probs])
     spq.spin_trotter_evolve_batch(probs, prec, dt, steps, init=spq.SPIN_INIT_RANDOM_PHASE)
+    assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for p in probs:
         Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, p["observed_site"],
