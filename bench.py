@@ -215,7 +215,8 @@ def run_star(spq, torch, steps, warmup):
             "steps": steps, "value": s32["value"], "unit": "amplitude-updates/s",
             "ms_per_step": s32["ms_per_step"], "passes_per_step": s32["passes_per_step"],
             "one_sweep_frac": s32["one_sweep_frac"],
-            "shape": {k: r32["info"][k] for k in ("tile_bits", "reg_bits", "lanes", "coalesce_bits")},
+            "shape": {k: r32["info"][k] for k in ("tile_bits", "reg_bits", "lanes", "coalesce_bits",
+                                                  "exchange")},
             "fp64": {"value": s64["value"], "ms_per_step": s64["ms_per_step"],
                      "passes_per_step": s64["passes_per_step"]},
             "err_P_fp32_vs_fp64": float(np.abs(r32["P"] - r64["P"]).max())}
@@ -269,7 +270,8 @@ def run_ensemble(spq, torch, L=7, steps=100, dt=0.05, draws=256):
 
 
 def shape_key(prec_name, info):
-    return "%s_k%d_r%d_c%d" % (prec_name, info["tile_bits"], info["reg_bits"], info["coalesce_bits"])
+    return "%s_k%d_r%d_c%d_x%d" % (prec_name, info["tile_bits"], info["reg_bits"], info["coalesce_bits"],
+                                   info.get("exchange", 1))
 
 
 def measured_traffic(key):
@@ -438,10 +440,11 @@ def main():
         out = spq.spin_autotune(prec, w["M"], w["J"], w["dt"], w["observed"], trial_steps=16)
         tuned["c64" if prec == spq.SPIN_C64 else "c128"] = {
             "seconds": time.perf_counter() - t0, "trial_steps": 16,
-            "candidates": [{k: r[k] for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine",
+            "candidates": [{k: r[k] for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine", "exchange",
                                                "ms_per_step", "trial_ms_per_step", "passes_per_step")}
                            for r in out["results"]],
-            "chosen": {k: getattr(out["best"], k) for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine")}}
+            "chosen": {k: getattr(out["best"], k) for k in ("tile_bits", "reg_bits", "coalesce_bits", "engine",
+                                                            "exchange")}}
         return out["best"]
 
     def with_graph(o):
@@ -501,7 +504,7 @@ def main():
         "passes_per_step": s["passes_per_step"],
         "launch": "hipGraph replay" if args.graph else "stream",
         "plan_seconds": head["plan_s"],
-        "shape": {k: head["info"][k] for k in ("tile_bits", "reg_bits", "lanes", "coalesce_bits")},
+        "shape": {k: head["info"][k] for k in ("tile_bits", "reg_bits", "lanes", "coalesce_bits", "exchange")},
         "hbm_gbs_per_step": s["hbm_gbs_per_step"],
         "one_sweep_frac": s["one_sweep_frac"],
     }

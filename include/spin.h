@@ -142,7 +142,13 @@ typedef struct {
                              and replayed on a library stream ordered after `stream`
                              (for calls that repeat); ignored by states held by one
                              workgroup and by the unfused schedule */
-    int32_t reserved[9];
+    int32_t exchange;     /* tiled path, stage exchanges through LDS: 0 = default (half
+                             tiles where the shape has such a kernel, else whole tiles);
+                             1 = whole tiles (one workgroup per CU, the next tile
+                             prefetched into registers); 2 = half tiles (one tile
+                             position stays in registers in every stage, the tile moves
+                             through LDS in two halves, two workgroups share a CU) */
+    int32_t reserved[8];
 } spin_options;
 
 /* As spin_trotter_evolve with explicit options (NULL = defaults). */
@@ -333,6 +339,8 @@ typedef struct {
     int32_t period_steps, period_passes;  /* repeating block of the plan (path 2) */
     int32_t stages_total;   /* register stages over all templates */
     int32_t engine;         /* stage arithmetic of path 2: 0 VALU butterflies, 1 MFMA matrices */
+    int32_t exchange;       /* stage exchanges of path 2: 1 whole tiles, 2 half tiles */
+    int32_t reserved_;
     int64_t launches;       /* pass-kernel launches for the whole call */
     int64_t factor_ops;     /* two-spin factor applications after merging, whole call */
     double passes_per_step; /* launches / n_steps (path 2) */

@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("reg_bits", ctypes.c_int32), ("coalesce_bits", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("no_merge", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("use_graph", ctypes.c_int32), ("exchange", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class TuneResult(ctypes.Structure):
@@ -77,6 +78,7 @@ class _PlanInfo(ctypes.Structure):
                 ("coalesce_bits", ctypes.c_int32), ("templates", ctypes.c_int32),
                 ("period_steps", ctypes.c_int32), ("period_passes", ctypes.c_int32),
                 ("stages_total", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("exchange", ctypes.c_int32), ("reserved_", ctypes.c_int32),
                 ("launches", ctypes.c_int64), ("factor_ops", ctypes.c_int64),
                 ("passes_per_step", ctypes.c_double)]
 

@@ -110,14 +110,14 @@ int scratch_get(hipStream_t st, size_t bytes, void** out) {
 
 // ------------------------------------------------------------- plan cache
 struct PlanKey {
-    int dev, prec, M, observed, k, r, nt, c, merge, engine, profile;
+    int dev, prec, M, observed, k, r, nt, c, merge, engine, profile, half;
     double dt;
     int64_t n_steps;
     std::vector<double> J;    // flattened couplings
     bool operator<(const PlanKey& o) const {
-        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, engine, profile, dt, n_steps, J) <
+        return std::tie(dev, prec, M, observed, k, r, nt, c, merge, engine, profile, half, dt, n_steps, J) <
                std::tie(o.dev, o.prec, o.M, o.observed, o.k, o.r, o.nt, o.c, o.merge, o.engine,
-                        o.profile, o.dt, o.n_steps, o.J);
+                        o.profile, o.half, o.dt, o.n_steps, o.J);
     }
 };
 
@@ -187,7 +187,10 @@ Shape choose_shape(int prec, int M, const spin_options* opt) {
     s.nt = (k - s.r >= 0 && k - s.r < 16) ? (1 << (k - s.r)) : 0;
     s.k = k;
     s.engine = opt ? opt->engine : 0;
-    s.valid = pass_shape_exists(f32, s.r, s.nt, s.engine);
+    const int ex = opt ? opt->exchange : 0;
+    const bool half_ok = s.engine == 0 && pass_half_exists(f32, s.r, s.nt);
+    s.half = ex == 2 || (ex == 0 && half_ok);
+    s.valid = s.half ? half_ok : pass_shape_exists(f32, s.r, s.nt, s.engine);
     s.res_cap = f32 ? 14 : 13;
     s.resident = M <= s.res_cap;
     return s;
@@ -227,11 +230,13 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
             pp.r = sh.r;
             pp.c = sh.c;
             pp.profile = key.profile != 0;
+            pp.half = sh.half;
             if (pp.profile) pp.max_meas = kMaxMeasProfile;
             dp->sp = plan_stream_best(key.M, J, key.dt, key.n_steps, key.observed, key.merge != 0, pp);
             dp->shape = PassShape{sh.r, sh.nt};
             dp->shape.engine = sh.engine;
             dp->shape.profile = pp.profile;
+            dp->shape.half = sh.half;
             dp->profile = pp.profile;
             dp->k = sh.k;
             const int64_t ntiles = int64_t(1) << (key.M - sh.k);
@@ -277,12 +282,13 @@ int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t
     if (!sh.resident && !sh.valid) {
         std::ostringstream os;
         os << "no pass kernel for tile_bits " << sh.k << " with reg_bits " << sh.r
-           << (sh.engine ? " and the matrix engine (complex64, tile_bits 14, reg_bits 5 only)" : "");
+           << (sh.engine ? " and the matrix engine (complex64, tile_bits 14, reg_bits 5 only)" : "")
+           << (sh.half ? " and half-tile exchanges" : "");
         return fail(SPIN_EUNSUPPORTED, os.str());
     }
     PlanKey key{dev, prec, M, observed, sh.k, sh.r, sh.nt, sh.c,
                 (opt && opt->no_merge) ? 0 : 1, sh.resident ? 0 : sh.engine,
-                profile ? 1 : 0, dt, sh.resident ? 0 : n_steps, {}};
+                profile ? 1 : 0, (sh.half && !sh.resident) ? 1 : 0, dt, sh.resident ? 0 : n_steps, {}};
     key.J.reserve(J.size() * 4);
     for (const Coupling& c : J) {
         key.J.push_back(c.i);
@@ -640,6 +646,9 @@ static int evolve_entry(void* psi, int32_t prec, int32_t M, const spin_coupling*
         if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
         if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
         if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
+        if (opt && (opt->exchange < 0 || opt->exchange > 2)) return fail(SPIN_EINVAL, "bad exchange option");
+        if (opt && opt->engine == 1 && opt->exchange == 2)
+            return fail(SPIN_EUNSUPPORTED, "the matrix engine exchanges whole tiles");
         if (profile && opt && opt->engine != 0)
             return fail(SPIN_EUNSUPPORTED, "the all-site profile runs on the butterfly engine only");
         std::vector<Coupling> Jv;
@@ -691,6 +700,9 @@ int spin_prepare_plan(int32_t prec, int32_t M, const spin_coupling* J, int32_t K
         if (observed_site < 0 || observed_site >= M) return fail(SPIN_EINVAL, "observed_site out of range");
         if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
         if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
+        if (opt && (opt->exchange < 0 || opt->exchange > 2)) return fail(SPIN_EINVAL, "bad exchange option");
+        if (opt && opt->engine == 1 && opt->exchange == 2)
+            return fail(SPIN_EUNSUPPORTED, "the matrix engine exchanges whole tiles");
         if (profile && opt && opt->engine != 0)
             return fail(SPIN_EUNSUPPORTED, "the all-site profile runs on the butterfly engine only");
         std::vector<Coupling> Jv;
@@ -757,6 +769,9 @@ int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double d
               int32_t observed, const spin_options* opt, HostPlan* hp) {
     if (opt && (opt->schedule < 0 || opt->schedule > 1)) return fail(SPIN_EINVAL, "bad schedule option");
     if (opt && (opt->engine < 0 || opt->engine > 1)) return fail(SPIN_EINVAL, "bad engine option");
+    if (opt && (opt->exchange < 0 || opt->exchange > 2)) return fail(SPIN_EINVAL, "bad exchange option");
+    if (opt && opt->engine == 1 && opt->exchange == 2)
+        return fail(SPIN_EUNSUPPORTED, "the matrix engine exchanges whole tiles");
     const bool profile = observed == SPIN_ALL_SITES;
     if (profile) observed = 0;
     if (profile && opt && opt->engine != 0)
@@ -781,6 +796,7 @@ int host_plan(int32_t prec, int32_t M, const std::vector<Coupling>& Jv, double d
             pp.r = hp->sh.r;
             pp.c = hp->sh.c;
             pp.profile = profile;
+            pp.half = hp->sh.half;
             if (profile) pp.max_meas = kMaxMeasProfile;
             hp->sp = plan_stream_best(M, Jv, dt, n_steps, observed, merge, pp);
         }
@@ -836,6 +852,7 @@ extern "C" int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling* 
         info->lanes = hp.sh.nt;
         info->coalesce_bits = hp.sh.c;
         info->engine = hp.sh.engine;
+        info->exchange = hp.sh.half ? 2 : 1;
         info->templates = int(hp.sp.passes.size());
         info->period_steps = hp.sp.period_steps;
         info->period_passes = hp.sp.period_passes;

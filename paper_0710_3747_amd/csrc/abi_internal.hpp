@@ -21,6 +21,7 @@ struct Shape {
     int c = 3;          // low address bits every tile keeps (coalescing)
     int res_cap = 14;   // largest M held by one workgroup
     int engine = 0;     // 0: VALU butterflies, 1: MFMA stage matrices
+    bool half = false;  // half-tile exchanges (two workgroups per CU)
     bool resident = false;
     bool valid = true;  // a pass kernel exists for (r, nt, engine)
 };

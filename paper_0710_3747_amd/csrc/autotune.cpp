@@ -25,7 +25,7 @@ namespace spinqp {
 namespace {
 
 struct Tuned {
-    int tile_bits, reg_bits, coalesce_bits, engine;
+    int tile_bits, reg_bits, coalesce_bits, engine, exchange;
     double ms_per_step;
 };
 
@@ -81,8 +81,9 @@ bool read_file(const char* path, std::map<std::string, Tuned>* out) {
         Tuned t;
         if (std::sscanf(line.c_str(),
                         " \"%199[^\"]\": {\"tile_bits\": %d, \"reg_bits\": %d, \"coalesce_bits\": %d, "
-                        "\"engine\": %d, \"ms_per_step\": %lf}",
-                        key, &t.tile_bits, &t.reg_bits, &t.coalesce_bits, &t.engine, &t.ms_per_step) == 6)
+                        "\"engine\": %d, \"exchange\": %d, \"ms_per_step\": %lf}",
+                        key, &t.tile_bits, &t.reg_bits, &t.coalesce_bits, &t.engine, &t.exchange,
+                        &t.ms_per_step) == 7)
             (*out)[key] = t;
     }
     return true;
@@ -93,16 +94,16 @@ int write_file(const char* path, const std::map<std::string, Tuned>& entries) {
     {
         std::ofstream out(tmp);
         if (!out) return fail(SPIN_EINVAL, std::string("cannot write ") + tmp);
-        out << "{\n \"format\": \"spinqp-autotune-1\",\n \"entries\": {\n";
+        out << "{\n \"format\": \"spinqp-autotune-2\",\n \"entries\": {\n";
         size_t n = 0;
         for (const auto& kv : entries) {
             char line[400];
             std::snprintf(line, sizeof line,
                           "  \"%s\": {\"tile_bits\": %d, \"reg_bits\": %d, \"coalesce_bits\": %d, "
-                          "\"engine\": %d, \"ms_per_step\": %.6f}%s\n",
+                          "\"engine\": %d, \"exchange\": %d, \"ms_per_step\": %.6f}%s\n",
                           kv.first.c_str(), kv.second.tile_bits, kv.second.reg_bits,
-                          kv.second.coalesce_bits, kv.second.engine, kv.second.ms_per_step,
-                          ++n < entries.size() ? "," : "");
+                          kv.second.coalesce_bits, kv.second.engine, kv.second.exchange,
+                          kv.second.ms_per_step, ++n < entries.size() ? "," : "");
             out << line;
         }
         out << " }\n}\n";
@@ -119,6 +120,7 @@ spin_options to_options(const Tuned& t) {
     o.reg_bits = t.reg_bits;
     o.coalesce_bits = t.coalesce_bits;
     o.engine = t.engine;
+    o.exchange = t.exchange;
     return o;
 }
 
@@ -126,13 +128,14 @@ spin_options to_options(const Tuned& t) {
 // matrix engine is not among them: a dense stage matrix costs about 20x the
 // flops of the butterflies it replaces and it removes no LDS exchange, so it
 // never wins on these workloads (it stays selectable through spin_options).
+// Exchange 2 = half tiles (two workgroups per CU), 1 = whole tiles.
 std::vector<Tuned> candidates(int32_t prec) {
     if (prec == SPIN_C64)
-        return {{14, 5, 4, 0, 0}, {14, 5, 5, 0, 0}, {14, 5, 6, 0, 0}, {14, 4, 5, 0, 0},
-                {14, 4, 4, 0, 0}, {13, 5, 5, 0, 0}, {13, 4, 5, 0, 0}, {14, 6, 5, 0, 0},
-                {12, 4, 5, 0, 0}};
-    return {{13, 4, 4, 0, 0}, {13, 5, 4, 0, 0}, {13, 3, 4, 0, 0}, {12, 4, 4, 0, 0},
-            {12, 3, 4, 0, 0}};
+        return {{14, 5, 4, 0, 2, 0}, {14, 5, 5, 0, 2, 0}, {14, 5, 6, 0, 2, 0}, {14, 6, 4, 0, 2, 0},
+                {14, 5, 4, 0, 1, 0}, {14, 5, 6, 0, 1, 0}, {14, 4, 4, 0, 1, 0}, {13, 5, 5, 0, 1, 0},
+                {13, 4, 4, 0, 1, 0}};
+    return {{13, 4, 4, 0, 2, 0}, {13, 5, 4, 0, 2, 0}, {13, 4, 4, 0, 1, 0}, {13, 5, 4, 0, 1, 0},
+            {12, 4, 4, 0, 1, 0}};
 }
 
 struct DeviceBuffers {

@@ -58,7 +58,8 @@ struct DevStage {
     int32_t ntb;              // number of thread bits (tile bits - register bits)
     int32_t obs_tq;           // thread bit holding the observed site, or -1
     int32_t obs_mask;         // register-index mask of the observed site (0 if none)
-    int32_t pad_;
+    int32_t xnext;            // 1: the exchange after this stage moves amplitudes between
+                              // waves (workgroup barrier); 0: within each wave only
     uint32_t tmask[16];       // LDS byte offset of thread bit q (zero past ntb)
     uint32_t rbit[8];         // LDS byte offset of register bit q
     // Global element offsets of thread bit q / register bit q, for the first
@@ -75,6 +76,9 @@ struct DevPass {
     int32_t nfree;            // number of non-tile bits
     int32_t obs_free_bit;     // global bit of the observed site if it is not a tile bit, else -1
     int32_t nmeas;            // measurements in this pass
+    int32_t tile_barrier;     // 1: workgroup barrier after each tile's stores
+    int32_t half;             // 1: half-tile exchanges (the top register bit of every stage
+                              // is the same tile position, which has no LDS image)
     int32_t pad_;
     int64_t meas_step[kMaxMeas];   // step label of measurement slot m (plus launch offset)
     int64_t free_mask;        // mask of the global bits not in the tile

@@ -353,6 +353,16 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Ordering of a wave's own LDS scatter before its gather: the exchange
+// moves amplitudes only between lanes of the wave, so no other wave reads
+// the slots (LDS operations of one wave complete in issue order; the fences
+// keep the compiler from moving the gather above the scatter).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Deposit of the bits of `x` into the set bits of `mask`, lowest first.
 __device__ __forceinline__ int64_t deposit(int64_t x, int64_t mask) {
     int64_t out = 0;
@@ -394,6 +404,36 @@ __device__ __forceinline__ void scatter(const C (&v)[1 << R], char* lds, uint32_
     for (int i = 1; i < (1 << R); ++i) {
         a ^= S.rbit[__builtin_ctz(i)];
         *reinterpret_cast<C*>(lds + a) = v[i ^ (i >> 1)];
+    }
+}
+
+// Gather / scatter of the half of a lane's registers whose top register bit
+// is H (the split position's value in a half-tile exchange), Gray-code order
+// over the lower R - 1 register bits.  The split position has no LDS image:
+// both halves use the same slots, one after the other.
+template <int R, int H, typename C, typename Stage>
+__device__ __forceinline__ void gather_half(C (&v)[1 << R], const char* lds, uint32_t pb,
+                                            const Stage& S) {
+    constexpr int B = 1 << (R - 1);
+    uint32_t a = pb;
+    v[H * B] = *reinterpret_cast<const C*>(lds + a);
+#pragma unroll
+    for (int i = 1; i < B; ++i) {
+        a ^= S.rbit[__builtin_ctz(i)];
+        v[H * B + (i ^ (i >> 1))] = *reinterpret_cast<const C*>(lds + a);
+    }
+}
+
+template <int R, int H, typename C, typename Stage>
+__device__ __forceinline__ void scatter_half(const C (&v)[1 << R], char* lds, uint32_t pb,
+                                             const Stage& S) {
+    constexpr int B = 1 << (R - 1);
+    uint32_t a = pb;
+    *reinterpret_cast<C*>(lds + a) = v[H * B];
+#pragma unroll
+    for (int i = 1; i < B; ++i) {
+        a ^= S.rbit[__builtin_ctz(i)];
+        *reinterpret_cast<C*>(lds + a) = v[H * B + (i ^ (i >> 1))];
     }
 }
 
@@ -493,11 +533,15 @@ __device__ __forceinline__ C& lds_at(char* lds, uint32_t byte) {
 // is loaded straight from HBM (lanes along the low address bits, so the
 // wave's accesses are contiguous runs) and the last one stored straight
 // back, in the pass's output layout; the stages in between exchange through
-// LDS.  Every wave has consumed its loads of a tile before the first LDS
-// barrier, so the stores after it cannot overtake another wave's loads.  A
-// one-stage pass never touches LDS and has no such barrier: its lanes store
-// exactly the addresses they loaded (the planner only makes one-stage passes
-// that keep the layout).  The next tile is prefetched into registers while
+// LDS, with a workgroup barrier where the exchange moves amplitudes between
+// waves and a wave-level ordering where it does not.  Every wave has
+// consumed its loads of a tile before the first workgroup barrier, so the
+// stores after it cannot overtake another wave's loads; a pass without such
+// a barrier keeps its wave positions and their address bits from the first
+// stage to the last, so each wave stores only addresses it loaded itself.  A
+// one-stage pass never touches LDS: its lanes store exactly the addresses
+// they loaded (the planner only makes one-stage passes that keep the
+// layout).  The next tile is prefetched into registers while
 // the current one is worked on.  Observables accumulate into accP/accN per
 // measurement slot of the pass.
 template <int R, typename C>
@@ -563,6 +607,23 @@ __device__ __forceinline__ void reg_half_sums(const C (&v)[1 << R], double& tot,
     tot = w[0];
 }
 
+// Same sums accumulated one register at a time (fewer live registers, more
+// adds), for kernels that share the CU with a second workgroup.
+template <int R, typename C>
+__device__ __forceinline__ void reg_half_sums_seq(const C (&v)[1 << R], double& tot, double (&half)[R]) {
+    tot = 0.0;
+#pragma unroll
+    for (int b = 0; b < R; ++b) half[b] = 0.0;
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        const double w = double(v[j].x) * double(v[j].x) + double(v[j].y) * double(v[j].y);
+        tot += w;
+#pragma unroll
+        for (int b = 0; b < R; ++b)
+            if ((j >> b) & 1) half[b] += w;
+    }
+}
+
 __device__ __forceinline__ double wave_sum_last(double v) {
     v = dpp_add<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
     v = dpp_add<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
@@ -590,7 +651,8 @@ __device__ __forceinline__ void prof_observe(const C (&v)[1 << R], int aux, int6
     reg_observe<R>(v, sign, mask, p, n);
 }
 
-template <typename T, int R, int NT, bool WRITES, int ENGINE = 0, bool PROFILE = false>
+template <typename T, int R, int NT, bool WRITES, int ENGINE = 0, bool PROFILE = false,
+          bool HALF = false>
 __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, const DevPass& P,
                                            const DevStage* __restrict__ stages,
                                            const DevOp<T>* __restrict__ ops, unsigned wperm,
@@ -611,22 +673,30 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
     int64_t m_hi = P.free_mask;
     for (unsigned g = G; g > 1; g >>= 1) m_hi &= m_hi - 1;
 
-    C pre[1 << R];
+    // Full-tile exchanges: the next tile's loads are issued into `pre` at
+    // the start of a tile and always (the last tile re-reads itself), so
+    // every iteration ends with the same memory ops outstanding -- prefetch
+    // loads, then stores -- and the copy out of `pre` only waits for the
+    // loads.  Half-tile exchanges leave room for a second workgroup on the
+    // CU instead of a prefetch: a tile's loads go straight into `v` and the
+    // other workgroup's work covers their latency.
+    C pre[HALF ? 1 : (1 << R)];
     int64_t hi = 0;
-    load_direct<R>(pre, psi, base_w + gin_t, S0.gr_in);
+    if constexpr (!HALF) load_direct<R>(pre, psi, base_w + gin_t, S0.gr_in);
 
-    // One tile.  The next tile's loads are issued at its start and always
-    // (the last tile re-reads itself), so every iteration ends with the same
-    // memory ops outstanding -- prefetch loads, then stores -- and the copy
-    // out of `pre` only waits for the loads.
     auto tile_body = [&](int64_t it_tile) {
         const int64_t base = base_w | hi;
         const int tile_sign = P.obs_free_bit >= 0 ? int((base >> P.obs_free_bit) & 1) : 0;
         C v[1 << R];
+        if constexpr (HALF) {
+            load_direct<R>(v, psi, base + gin_t, S0.gr_in);
+            if (it_tile + 1 < tiles_per_member) hi = next_submask(hi, m_hi);
+        } else {
 #pragma unroll
-        for (int j = 0; j < (1 << R); ++j) v[j] = pre[j];
-        if (it_tile + 1 < tiles_per_member) hi = next_submask(hi, m_hi);
-        load_direct<R>(pre, psi, (base_w | hi) + gin_t, S0.gr_in);
+            for (int j = 0; j < (1 << R); ++j) v[j] = pre[j];
+            if (it_tile + 1 < tiles_per_member) hi = next_submask(hi, m_hi);
+            load_direct<R>(pre, psi, (base_w | hi) + gin_t, S0.gr_in);
+        }
 
         for (int si = 0; si < P.nstage; ++si) {
             const DevStage& S = stages[P.stage0 + si];
@@ -634,7 +704,8 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
 #pragma unroll
             for (int b = 0; b < R; ++b) rb.rbit[b] = S.rbit[b];
             const uint32_t pb = stage_base(S, tid);
-            if (si > 0) gather<R>(v, ldsb, pb, rb);
+            if constexpr (!HALF)
+                if (si > 0) gather<R>(v, ldsb, pb, rb);
             const int sign = tile_sign ^ (S.obs_tq >= 0 ? ((tid >> S.obs_tq) & 1) : 0);
             const int o1 = S.op0 + S.nop;
             int o = S.op0;
@@ -656,7 +727,8 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                         // each squared once; wave sums go to the wave's LDS
                         // row (pacc / nacc), one row per wave.
                         double tot, half[R];
-                        reg_half_sums<R>(v, tot, half);
+                        if constexpr (HALF) reg_half_sums_seq<R>(v, tot, half);
+                        else reg_half_sums<R>(v, tot, half);
                         const bool last = (tid & 63) == 63;
                         while (o < o1 && ops[o].code == kOpMeas) {
                             const int aux = ops[o].aux;
@@ -682,6 +754,19 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
                             ++o;
                         }
                         continue;
+                    } else if constexpr (HALF) {
+                        // wave sums into the wave's own LDS row (pacc: slot
+                        // m holds P at 2m, N at 2m + 1), no accumulator
+                        // registers
+                        const int slot = ops[o].aux;
+                        double p = 0.0, n = 0.0;
+                        reg_observe<R>(v, sign, S.obs_mask, p, n);
+                        p = wave_sum_last(p);
+                        n = wave_sum_last(n);
+                        if ((tid & 63) == 63) {
+                            pacc[2 * slot] += p;
+                            pacc[2 * slot + 1] += n;
+                        }
                     } else {
                         const int slot = ops[o].aux;
                         double p = 0.0, n = 0.0;
@@ -695,13 +780,44 @@ __device__ __forceinline__ void pass_tiles(typename CT<T>::c* __restrict__ psi, 
             }
             if (si + 1 < P.nstage) {
                 // A lane scatters to exactly the LDS slots the next stage's
-                // lanes gather after the barrier.
-                scatter<R>(v, ldsb, pb, rb);
-                lds_barrier();
+                // lanes gather after the barrier.  When both stages keep the
+                // same positions on the wave bits, those slots belong to the
+                // wave's own lanes and only the wave is ordered.
+                const bool xw = S.xnext != 0;
+                auto sync = [&]() {
+                    if (xw) lds_barrier();
+                    else wave_lds_sync();
+                };
+                if constexpr (HALF) {
+                    // The split position stays on the top register bit:
+                    // half 0 through the LDS, then half 1 through the same
+                    // slots.  A lane's gather slots in the next stage are its
+                    // scatter slots there, so the next exchange needs no
+                    // ordering before its first scatter; inside this one the
+                    // second scatter waits for every first gather.
+                    const DevStage& S2 = stages[P.stage0 + si + 1];
+                    RegBits<R> rb2;
+#pragma unroll
+                    for (int b = 0; b < R; ++b) rb2.rbit[b] = S2.rbit[b];
+                    const uint32_t pb2 = stage_base(S2, tid);
+                    scatter_half<R, 0>(v, ldsb, pb, rb);
+                    sync();
+                    gather_half<R, 0>(v, ldsb, pb2, rb2);
+                    sync();
+                    scatter_half<R, 1>(v, ldsb, pb, rb);
+                    sync();
+                    gather_half<R, 1>(v, ldsb, pb2, rb2);
+                } else {
+                    scatter<R>(v, ldsb, pb, rb);
+                    sync();
+                }
             }
         }
         if constexpr (WRITES) store_direct<R>(v, psi, base + gout_t, SL.gr_out);
-        lds_barrier();    // the last gathers are done before the next tile's scatters
+        // the last gathers are done before the next tile's scatters, unless
+        // the last and first stages keep the same wave positions (then every
+        // wave's slots are its own across the tile boundary)
+        if (P.tile_barrier) lds_barrier();
     };
     tile_body(0);
     for (int64_t it_tile = 1; it_tile < tiles_per_member; ++it_tile) tile_body(it_tile);
@@ -723,8 +839,10 @@ __device__ __forceinline__ void slot_sum(const double (&accP)[kMaxMeas],
 // --------------------------------------------------------------- k_pass
 // partials: [slot][nwg][2] (P, N), or with PROFILE [slot][nwg][M + 1] (P of
 // every site, then N).
-template <typename T, int R, int NT, bool WRITES, int ENGINE, bool PROFILE>
-__global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi,
+// HALF: half-tile exchanges, LDS for half a tile, no register prefetch, and
+// registers capped so that two workgroups share a CU.
+template <typename T, int R, int NT, bool WRITES, int ENGINE, bool PROFILE, bool HALF>
+__global__ __launch_bounds__(NT, HALF ? 2 * NT / 256 : 1) void k_pass(typename CT<T>::c* __restrict__ psi,
                                              const DevPass* __restrict__ passes,
                                              const DevStage* __restrict__ stages,
                                              const DevOp<T>* __restrict__ ops, int pass_index,
@@ -733,7 +851,7 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
                                              const float* __restrict__ mats) {
     using C = typename CT<T>::c;
     constexpr int K = R + __builtin_ctz(NT);
-    __shared__ C lds[1 << K];
+    __shared__ C lds[HALF ? (1 << (K - 1)) : (1 << K)];
     __shared__ double red[2 * (NT / 64)];
     const DevPass& P = passes[pass_index];
     double accP[kMaxMeas], accN[kMaxMeas];
@@ -756,9 +874,9 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
             for (int m = 0; m < kMaxMeasProfile; ++m) pacc[wave][m] = 0.0;
             for (int m = 0; m < kMaxMeas; ++m) nacc[wave][m] = 0.0;
         }
-        pass_tiles<T, R, NT, WRITES, ENGINE, true>(psi, P, stages, ops, wperm, G, tiles_per_wg,
-                                                   reinterpret_cast<char*>(lds), accP, accN, mats,
-                                                   pacc[wave], nacc[wave]);
+        pass_tiles<T, R, NT, WRITES, ENGINE, true, HALF>(psi, P, stages, ops, wperm, G, tiles_per_wg,
+                                                         reinterpret_cast<char*>(lds), accP, accN, mats,
+                                                         pacc[wave], nacc[wave]);
         __syncthreads();
         const int M = P.k + P.nfree;
         auto dst = [&](int64_t step) {
@@ -780,8 +898,33 @@ __global__ __launch_bounds__(NT) void k_pass(typename CT<T>::c* __restrict__ psi
         }
         return;
     }
-    pass_tiles<T, R, NT, WRITES, ENGINE>(psi, P, stages, ops, wperm, G, tiles_per_wg,
-                                         reinterpret_cast<char*>(lds), accP, accN, mats);
+    if constexpr (HALF) {
+        // per-wave observable rows; fixed-order sum over the waves
+        constexpr int NW = NT / 64;
+        __shared__ double wacc[NW][2 * kMaxMeas];
+        const int wave = threadIdx.x / 64;
+        if ((threadIdx.x & 63) == 63)
+            for (int m = 0; m < 2 * kMaxMeas; ++m) wacc[wave][m] = 0.0;
+        pass_tiles<T, R, NT, WRITES, ENGINE, false, true>(psi, P, stages, ops, wperm, G, tiles_per_wg,
+                                                          reinterpret_cast<char*>(lds), accP, accN,
+                                                          mats, wacc[wave]);
+        __syncthreads();
+        if (threadIdx.x < P.nmeas) {
+            const int m = threadIdx.x;
+            double p = 0.0, n = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                p += wacc[w][2 * m];
+                n += wacc[w][2 * m + 1];
+            }
+            const int64_t s = step_offset + P.meas_step[m];
+            double* dst = partials + ((size_t)(s % ch) * nwg + blockIdx.x) * 2;
+            dst[0] = p;
+            dst[1] = n;
+        }
+        return;
+    }
+    pass_tiles<T, R, NT, WRITES, ENGINE, false, false>(psi, P, stages, ops, wperm, G, tiles_per_wg,
+                                                       reinterpret_cast<char*>(lds), accP, accN, mats);
     for (int m = 0; m < P.nmeas; ++m) {
         double p, n;
         slot_sum<NT>(accP, accN, m, red, p, n);
@@ -1096,20 +1239,25 @@ hipError_t launch_factor(void* psi, int M, int lo, int hi, double t, double s, d
     return hipGetLastError();
 }
 
-template <typename T, int R, int NT, int ENGINE = 0, bool PROFILE = false>
+template <typename T, int R, int NT, int ENGINE = 0, bool PROFILE = false, bool HALF = false>
 static hipError_t pass_one(bool writes, void* psi, const DevPass* passes, const DevStage* stages,
                            const DevOp<T>* ops, int pass_index, int64_t tiles_per_wg, int nwg,
                            double* partials, int64_t step_offset, int ch, const float* mats,
                            hipStream_t st) {
     if (writes)
-        hipLaunchKernelGGL((k_pass<T, R, NT, true, ENGINE, PROFILE>), dim3(nwg), dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_pass<T, R, NT, true, ENGINE, PROFILE, HALF>), dim3(nwg), dim3(NT), 0, st,
                            reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
                            pass_index, tiles_per_wg, partials, step_offset, ch, nwg, mats);
     else
-        hipLaunchKernelGGL((k_pass<T, R, NT, false, ENGINE, PROFILE>), dim3(nwg), dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_pass<T, R, NT, false, ENGINE, PROFILE, HALF>), dim3(nwg), dim3(NT), 0, st,
                            reinterpret_cast<typename CT<T>::c*>(psi), passes, stages, ops,
                            pass_index, tiles_per_wg, partials, step_offset, ch, nwg, mats);
     return hipGetLastError();
+}
+
+bool pass_half_exists(bool f32, int r, int nt) {
+    if (f32) return (r == 5 && nt == 512) || (r == 6 && nt == 256);
+    return (r == 4 && nt == 512) || (r == 5 && nt == 256);
 }
 
 bool pass_shape_exists(bool f32, int r, int nt, int engine) {
@@ -1135,6 +1283,24 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
         }
     }
     if (sh.engine != 0) return hipErrorInvalidValue;
+    if (sh.half) {
+#define SPIN_HALF(RR, NTT)                                                                        \
+    if (sh.r == RR && sh.nt == NTT)                                                               \
+        return sh.profile                                                                         \
+                   ? pass_one<T, RR, NTT, 0, true, true>(sh.writes, psi, passes, stages, ops,     \
+                                                         pass_index, tiles_per_wg, nwg, partials, \
+                                                         step_offset, ch, nullptr, st)            \
+                   : pass_one<T, RR, NTT, 0, false, true>(sh.writes, psi, passes, stages, ops,    \
+                                                          pass_index, tiles_per_wg, nwg, partials,\
+                                                          step_offset, ch, nullptr, st);
+        if constexpr (sizeof(T) == 4) {
+            SPIN_HALF(5, 512) SPIN_HALF(6, 256)
+        } else {
+            SPIN_HALF(4, 512) SPIN_HALF(5, 256)
+        }
+#undef SPIN_HALF
+        return hipErrorInvalidValue;
+    }
 #define SPIN_PASS(RR, NTT)                                                                   \
     if (sh.r == RR && sh.nt == NTT)                                                          \
         return sh.profile                                                                    \

@@ -46,9 +46,12 @@ struct PassShape {
     int engine = 0;       // 0: VALU butterflies; 1: MFMA stage matrices (complex64, r = 5, nt = 512)
     const float* mats = nullptr;   // engine 1: device matrix table
     bool profile = false;          // per-site observables: profile partials [slot][nwg][M + 1]
+    bool half = false;             // half-tile exchanges, two workgroups per CU (engine 0)
 };
 // Whether a pass kernel is instantiated for (precision, r, nt, engine).
 bool pass_shape_exists(bool f32, int r, int nt, int engine);
+// Whether a half-tile-exchange pass kernel is instantiated for (precision, r, nt).
+bool pass_half_exists(bool f32, int r, int nt);
 
 template <typename T>
 hipError_t launch_init(void* psi, int M, int n, uint64_t seed, hipStream_t st);

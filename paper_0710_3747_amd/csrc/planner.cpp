@@ -432,16 +432,59 @@ std::vector<Op> gen_sequence(int M, const std::vector<Coupling>& J, double dt, i
 }  // namespace
 
 // ----------------------------------------------------------------- stages
-void plan_stages_coalesced(HostPass& pass, int r, int c, int beam) {
+void plan_stages_coalesced(HostPass& pass, int r, int c, int beam, bool half) {
     uint32_t af = 0, al = 0;
-    for (size_t p = 0; p < pass.sites.size(); ++p) {
+    const int k = int(pass.sites.size());
+    for (int p = 0; p < k; ++p) {
         if (pass.bit_in[p] < c) af |= 1u << p;
         if (pass.bit_out[p] < c) al |= 1u << p;
     }
-    plan_stages(pass, r, af, al, beam);
+    pass.split = -1;
+    if (!half || k < 2 || r < 2) {
+        plan_stages(pass, r, af, al, beam);
+        return;
+    }
+    // split position: the one whose greedy staging is shortest (ties: the
+    // position with the most factors), staged again with the requested beam
+    std::vector<int> nops(k, 0), local(kMaxSites, -1);
+    for (int p = 0; p < k; ++p) local[pass.sites[p]] = p;
+    for (const Op& op : pass.ops)
+        if (op.kind == 0) {
+            ++nops[local[op.i]];
+            ++nops[local[op.j]];
+        }
+    int best = -1;
+    size_t best_n = 0;
+    for (int h = 0; h < k; ++h) {
+        if (((af | al) >> h) & 1u) continue;
+        HostPass t = pass;
+        try {
+            plan_stages(t, r, af, al, 1, 1u << h);
+        } catch (const std::runtime_error&) {
+            continue;
+        }
+        if (best < 0 || t.stages.size() < best_n ||
+            (t.stages.size() == best_n && nops[h] > nops[best])) {
+            best = h;
+            best_n = t.stages.size();
+        }
+    }
+    if (best < 0) throw std::runtime_error("planner: no split position for a half-tile pass");
+    plan_stages(pass, r, af, al, beam, 1u << best);
+    pass.split = best;
+    // the split position on the top register bit of every stage
+    for (HostStage& st : pass.stages) {
+        std::vector<int> regs;
+        for (int q : st.regs)
+            if (q != best) regs.push_back(q);
+        if (int(regs.size()) + 1 != int(st.regs.size())) throw std::runtime_error("planner: split position lost");
+        regs.push_back(best);
+        st.regs = regs;
+    }
 }
 
-void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_last, int beam) {
+void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_last, int beam,
+                 uint32_t force) {
     const int k = int(pass.sites.size());
     const int nops = int(pass.ops.size());
     std::vector<int> local(kMaxSites, -1);
@@ -495,9 +538,9 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_las
         std::vector<Cand> out;
         for (int seed : seeds) {
             std::vector<int> h = st.head;
-            uint32_t S = 0;
-            if (seed >= 0) S = (1u << li[seed]) | (1u << lj[seed]);
-            if (S & avoid) S = 0;
+            uint32_t S = force;
+            if (seed >= 0) S = force | (1u << li[seed]) | (1u << lj[seed]);
+            if ((S & avoid) || __builtin_popcount(S) > r) S = force;
             std::vector<int> got;
             std::vector<char> taken(nops, 0);
             int cnt = 0;
@@ -530,7 +573,7 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_las
     };
     auto advance = [&](const State& st, const Cand& c) {
         State nx = st;
-        uint32_t S = c.S;
+        uint32_t S = c.S | force;
         const uint32_t avoid = st.stages.empty() ? avoid_first : 0u;
         // Fill the register set up to r positions, highest positions first
         // (keeps the lanes on low positions), never the avoided ones and
@@ -621,8 +664,11 @@ void plan_stages(HostPass& pass, int r, uint32_t avoid_first, uint32_t avoid_las
         if (extra == 2) throw std::runtime_error("planner: cannot place the last stage");
         HostStage st;
         const uint32_t av = pass.stages.empty() ? avoid_first : avoid_last;
+        if (force & av) throw std::runtime_error("planner: forced position on a low bit");
+        for (int p = 0; p < k; ++p)
+            if ((force >> p) & 1u) st.regs.push_back(p);
         for (int p = k - 1; p >= 0 && int(st.regs.size()) < std::min(r, k); --p)
-            if (!((av >> p) & 1u)) st.regs.push_back(p);
+            if (!((av >> p) & 1u) && !((force >> p) & 1u)) st.regs.push_back(p);
         std::sort(st.regs.begin(), st.regs.end());
         if (int(st.regs.size()) < std::min(r, k)) throw std::runtime_error("planner: tile too small");
         pass.stages.push_back(std::move(st));
@@ -669,7 +715,7 @@ static StreamPlan plan_stream_per_step(int M, const std::vector<Coupling>& J, do
         auto ap = sc.next_pass(forced, &T);
         plan.passes.push_back(make_pass(sb.ops, ap, T, M));
     }
-    for (auto& p : plan.passes) plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c);
+    for (auto& p : plan.passes) plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c, 1, pp.half);
     for (int t = 0; t < nobs0; ++t) {
         plan.launch_tmpl.push_back(t);
         plan.launch_offset.push_back(0);
@@ -766,7 +812,8 @@ std::vector<HostPass> plan_block(int M, const std::vector<Coupling>& J, double d
 }
 
 void finish_stages(StreamPlan& plan, const PassParams& pp) {
-    for (auto& p : plan.passes) plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c);
+    for (auto& p : plan.passes)
+        plan_stages_coalesced(p, std::min(pp.r, int(p.sites.size())), pp.c, 1, pp.half);
 }
 
 // Blocks of `W` steps repeated verbatim: the first carries the step-0
@@ -980,8 +1027,11 @@ StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, in
     if (nv > 1)
         for (HostPass& hp : best.passes) {
             HostPass alt = hp;
-            plan_stages_coalesced(alt, std::min(pp.r, int(alt.sites.size())), pp.c, 32);
-            if (alt.stages.size() < hp.stages.size()) hp.stages = std::move(alt.stages);
+            plan_stages_coalesced(alt, std::min(pp.r, int(alt.sites.size())), pp.c, 32, pp.half);
+            if (alt.stages.size() < hp.stages.size()) {
+                hp.stages = std::move(alt.stages);
+                hp.split = alt.split;
+            }
         }
     return best;
 }
@@ -1128,6 +1178,71 @@ void choose_lanes(std::vector<int>& tp, const std::vector<uint32_t>& img, int el
     tp = out;
 }
 
+// Positions on the wave bits of every stage of a multi-stage pass (as
+// masks of tile-local positions; zero where the workgroup is one wave).
+// The stages are cut into maximal runs whose register positions leave at
+// least `nw` positions free; a run's wave positions are free in all its
+// stages.  The first stage keeps its 6 lowest-input-bit thread positions on
+// the lane bits and the last stage its 6 lowest-output-bit ones, so global
+// accesses keep their contiguous runs.  The first run's wave positions are
+// also the last run's when both allow it (no barrier at the tile end), and
+// positions that keep their address bit are preferred.
+std::vector<uint32_t> wave_bits_plan(const HostPass& hp) {
+    const int k = int(hp.sites.size()), nst = int(hp.stages.size());
+    std::vector<uint32_t> w(nst, 0);
+    if (nst == 0) return w;
+    const int nw = k - int(hp.stages[0].regs.size()) - 6;
+    if (nw <= 0 || nst == 1) return w;
+    const uint32_t all = (1u << k) - 1;
+    std::vector<uint32_t> forbid(nst, 0);
+    for (int si = 0; si < nst; ++si)
+        for (int p : hp.stages[si].regs) forbid[si] |= 1u << p;
+    auto low6 = [&](int si, const std::vector<int>& bit) {
+        std::vector<int> tp;
+        for (int p = 0; p < k; ++p)
+            if (!((forbid[si] >> p) & 1u)) tp.push_back(p);
+        std::stable_sort(tp.begin(), tp.end(), [&](int a, int b) { return bit[a] < bit[b]; });
+        uint32_t m = 0;
+        for (int q = 0; q < 6 && q < int(tp.size()); ++q) m |= 1u << tp[q];
+        return m;
+    };
+    const uint32_t lo_first = low6(0, hp.bit_in), lo_last = low6(nst - 1, hp.bit_out);
+    forbid[0] |= lo_first;
+    forbid[nst - 1] |= lo_last;
+    // maximal runs
+    std::vector<std::pair<int, int>> runs;
+    std::vector<uint32_t> avail;
+    for (int s0 = 0; s0 < nst;) {
+        uint32_t used = forbid[s0];
+        if (__builtin_popcount(all & ~used) < nw) throw std::runtime_error("encode: no room for wave bits");
+        int e = s0 + 1;
+        while (e < nst && __builtin_popcount(all & ~(used | forbid[e])) >= nw) used |= forbid[e++];
+        runs.push_back({s0, e});
+        avail.push_back(all & ~used);
+        s0 = e;
+    }
+    auto pick = [&](uint32_t cand) {
+        uint32_t m = 0;
+        int n = 0;
+        for (int pass2 = 0; pass2 < 2 && n < nw; ++pass2)
+            for (int p = k - 1; p >= 0 && n < nw; --p) {
+                if (!((cand >> p) & 1u) || ((m >> p) & 1u)) continue;
+                if (pass2 == 0 && hp.bit_in[p] != hp.bit_out[p]) continue;
+                m |= 1u << p;
+                ++n;
+            }
+        return m;
+    };
+    const size_t nr = runs.size();
+    std::vector<uint32_t> rw(nr);
+    for (size_t r = 0; r < nr; ++r) rw[r] = pick(avail[r]);
+    if (nr > 1 && __builtin_popcount(avail[0] & avail[nr - 1]) >= nw)
+        rw[0] = rw[nr - 1] = pick(avail[0] & avail[nr - 1]);
+    for (size_t r = 0; r < nr; ++r)
+        for (int si = runs[r].first; si < runs[r].second; ++si) w[si] = rw[r];
+    return w;
+}
+
 uint32_t apply_layout(const std::vector<uint32_t>& img, uint32_t l) {
     uint32_t o = 0;
     for (size_t p = 0; p < img.size(); ++p)
@@ -1196,6 +1311,7 @@ void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, boo
     dp.stage0 = int(out.stages.size());
     dp.nstage = int(hp.stages.size());
     dp.writes = hp.writes ? 1 : 0;
+    dp.half = hp.split >= 0 ? 1 : 0;
     if (hp.stages.empty()) throw std::runtime_error("encode: pass without stages");
     std::vector<int> local(kMaxSites, -1);
     int64_t tile_bits = 0;
@@ -1219,28 +1335,87 @@ void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, boo
     // of a multi-stage pass take positions in order of output bit, so that
     // consecutive lanes store consecutive addresses; elsewhere position
     // order, which is input-bit order.
-    std::vector<std::vector<int>> tpos_all;
-    for (size_t si = 0; si < hp.stages.size(); ++si) {
-        uint32_t rmask = 0;
-        for (int p : hp.stages[si].regs) rmask |= 1u << p;
-        std::vector<int> tp;
-        for (int p = 0; p < k; ++p)
-            if (!(rmask & (1u << p))) tp.push_back(p);
-        if (si + 1 == hp.stages.size() && si > 0)
-            std::stable_sort(tp.begin(), tp.end(),
-                             [&](int a, int b) { return hp.bit_out[a] < hp.bit_out[b]; });
-        tpos_all.push_back(tp);
-    }
+    //
+    // Wave bits: thread bits 6 and up select the wave.  A stage exchange
+    // that keeps the same positions on the wave bits (in the same order)
+    // moves every amplitude within its wave, so the wave's LDS slots are its
+    // own and no workgroup barrier is needed (wave_bits_plan).
     for (int p = 1; p < k; ++p)
         if (hp.bit_in[p] <= hp.bit_in[p - 1]) throw std::runtime_error("encode: input bits not increasing");
     if (hp.stages.size() == 1 && hp.bit_in != hp.bit_out)
         throw std::runtime_error("encode: one-stage pass that moves amplitudes");
+    const int nst = int(hp.stages.size());
+    std::vector<uint32_t> wmask(nst, 0);
+    if (!fixed_swizzle) wmask = wave_bits_plan(hp);
+    std::vector<std::vector<int>> tpos_all, lanes_all;
+    for (int si = 0; si < nst; ++si) {
+        uint32_t rmask = 0;
+        for (int p : hp.stages[si].regs) rmask |= 1u << p;
+        std::vector<int> tp, wv;
+        for (int p = 0; p < k; ++p)
+            if (!(rmask & (1u << p))) ((wmask[si] >> p) & 1u ? wv : tp).push_back(p);
+        if (si + 1 == nst && si > 0)
+            std::stable_sort(tp.begin(), tp.end(),
+                             [&](int a, int b) { return hp.bit_out[a] < hp.bit_out[b]; });
+        lanes_all.push_back(tp);
+        tp.insert(tp.end(), wv.begin(), wv.end());
+        tpos_all.push_back(tp);
+    }
     std::vector<uint32_t> img(k);
     if (fixed_swizzle) {
         for (int p = 0; p < k; ++p) img[p] = lds_swizzle<eb>(1u << p);
+    } else if (hp.split >= 0) {
+        // half-tile exchange: the LDS holds one half at a time, addressed by
+        // the other k - 1 positions; the split position has no image (both
+        // halves use the same slots)
+        const int h = hp.split;
+        for (const HostStage& st : hp.stages)
+            if (st.regs.empty() || st.regs.back() != h)
+                throw std::runtime_error("encode: split position not on the top register bit");
+        auto comp = [&](int p) { return p < h ? p : p - 1; };
+        std::vector<std::vector<int>> pat;
+        for (const auto& lv : lanes_all) {
+            std::vector<int> q;
+            for (int p : lv) q.push_back(comp(p));
+            pat.push_back(q);
+        }
+        const std::vector<uint32_t> im = search_layout(k - 1, eb, pat, uint64_t(k) * 131 + hp.ops.size());
+        for (int p = 0; p < k; ++p) img[p] = p == h ? 0u : im[comp(p)];
+        for (int si = 1; si + 1 < nst; ++si) {
+            std::vector<int> tp = lanes_all[si];
+            choose_lanes(tp, img, eb);
+            for (size_t q = 0; q < tp.size(); ++q) tpos_all[si][q] = tp[q];
+        }
     } else {
-        img = search_layout(k, eb, tpos_all, uint64_t(k) * 131 + hp.ops.size());
-        for (size_t si = 1; si + 1 < tpos_all.size(); ++si) choose_lanes(tpos_all[si], img, eb);
+        img = search_layout(k, eb, lanes_all, uint64_t(k) * 131 + hp.ops.size());
+        for (int si = 1; si + 1 < nst; ++si) {
+            // reorder the lane positions only; the wave positions stay last
+            std::vector<int> tp = lanes_all[si];
+            choose_lanes(tp, img, eb);
+            for (size_t q = 0; q < tp.size(); ++q) tpos_all[si][q] = tp[q];
+        }
+    }
+    // The exchange after stage si crosses waves (workgroup barrier) when the
+    // wave positions change.  A wave's stores of a tile may overlap another
+    // wave's loads of it unless both keep the same wave positions on the
+    // same address bits; then some exchange of the tile must have a
+    // workgroup barrier (every wave has consumed its loads once it has made
+    // its first exchange), and the first one gets it.  The tile-end barrier
+    // is needed when the last stage's waves differ from the first stage's
+    // (the next tile's first scatters would land in slots other waves still
+    // read).
+    std::vector<int> xnext(std::max(nst - 1, 0), 0);
+    bool any_cross = false;
+    for (int si = 0; si + 1 < nst; ++si) {
+        xnext[si] = (fixed_swizzle || wmask[si] != wmask[si + 1]) ? 1 : 0;
+        any_cross |= xnext[si] != 0;
+    }
+    if (nst > 1) {
+        bool keep_bits = true;
+        for (int p = 0; p < k; ++p)
+            if ((wmask[0] >> p) & 1u) keep_bits &= hp.bit_in[p] == hp.bit_out[p];
+        if (!any_cross && !(wmask[0] == wmask[nst - 1] && keep_bits)) xnext[0] = 1;
+        dp.tile_barrier = (fixed_swizzle || wmask[0] != wmask[nst - 1]) ? 1 : 0;
     }
     auto byte_off = [&](uint32_t l) { return apply_layout(img, l) * uint32_t(eb); };
 
@@ -1251,6 +1426,7 @@ void encode_pass(const HostPass& hp, int M, int observed, DevTables<T>& out, boo
         ds.op0 = int(out.ops.size());
         const int rr = int(hs.regs.size());
         ds.ntb = k - rr;
+        ds.xnext = (int(si) + 1 < nst) ? xnext[si] : 1;
         const std::vector<int>& tq = tpos_all[si];
         for (int q = 0; q < ds.ntb; ++q) {
             ds.tmask[q] = byte_off(1u << tq[q]);

@@ -62,6 +62,8 @@ struct HostStage {
 };
 
 struct HostPass {
+    int split = -1;            // tile-local position held in registers by every stage (the
+                               // top register bit), or -1; see PassParams::half
     std::vector<int> sites;    // tile-local position p -> site
     std::vector<int> bit_in;   // tile-local position p -> global bit before the pass (increasing)
     std::vector<int> bit_out;  // tile-local position p -> global bit after the pass
@@ -77,6 +79,11 @@ struct PassParams {
     int c = 4;                 // low global bits every tile must contain
     int max_meas = kMaxMeas;
     bool profile = false;      // observables of every site (max_meas kMaxMeasProfile)
+    // Half-tile exchanges: one tile position (chosen per pass) is a register
+    // position of every stage, on the top register bit, so a stage exchange
+    // can move the tile through LDS in two halves (the position's two
+    // values), each half through the same LDS slots.
+    bool half = false;
     // Scheduling variant (plan_stream tries several and keeps the cheapest
     // by the cost model below):
     int window = 3;            // steps a pass may run ahead of the oldest pending op
@@ -112,11 +119,14 @@ struct StreamPlan {
 // positions holding the coalescing address bits (avoid_first / avoid_last,
 // masks of tile-local positions); empty stages are added where needed.
 // beam: width of the search over stage sequences (1 = greedy).
+// force: positions in the register set of every stage.
 void plan_stages(HostPass& pass, int r, uint32_t avoid_first = 0, uint32_t avoid_last = 0,
-                 int beam = 1);
+                 int beam = 1, uint32_t force = 0);
 // Same, with the masks taken from the pass's layouts: positions whose input
-// (output) global bit is below c.
-void plan_stages_coalesced(HostPass& pass, int r, int c, int beam = 1);
+// (output) global bit is below c.  half: also choose the pass's split
+// position (HostPass::split) and keep it on the top register bit of every
+// stage.
+void plan_stages_coalesced(HostPass& pass, int r, int c, int beam = 1, bool half = false);
 
 // Full streaming plan for one scheduling variant: sequence, passes, period
 // search, stages.

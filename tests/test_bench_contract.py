@@ -25,12 +25,11 @@ def counters_current():
     return h.hexdigest()[:16] == t["kernel_source_sha256_16"]
 
 
-@pytest.mark.parametrize("prec,k,r,c", [("c64", 14, 5, 4), ("c64", 14, 4, 4), ("c64", 14, 5, 6),
-                                        ("c128", 13, 4, 4)])
-def test_measured_traffic_per_launch_shape(prec, k, r, c):
+@pytest.mark.parametrize("prec,k,r,c,x", [("c64", 14, 5, 4, 2), ("c64", 14, 5, 4, 1), ("c128", 13, 4, 4, 2)])
+def test_measured_traffic_per_launch_shape(prec, k, r, c, x):
     if not counters_current():
         pytest.skip("kernel source changed since the HBM counters were taken (bench reports null)")
-    key = bench.shape_key(prec, dict(tile_bits=k, reg_bits=r, coalesce_bits=c))
+    key = bench.shape_key(prec, dict(tile_bits=k, reg_bits=r, coalesce_bits=c, exchange=x))
     t = bench.measured_traffic(key)
     alg = 2 * 2 ** 30 * (8 if prec == "c64" else 16)
     assert t is not None, key
@@ -39,7 +38,7 @@ def test_measured_traffic_per_launch_shape(prec, k, r, c):
 
 
 def test_unmeasured_shape_reports_no_traffic():
-    key = bench.shape_key("c64", dict(tile_bits=12, reg_bits=4, coalesce_bits=5))
+    key = bench.shape_key("c64", dict(tile_bits=12, reg_bits=4, coalesce_bits=5, exchange=1))
     assert bench.measured_traffic(key) is None
 
 

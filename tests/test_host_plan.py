@@ -11,6 +11,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -186,15 +187,23 @@ def test_long_ladder_plan_is_periodic_and_fused():
 
 def test_matrix_engine_option_checks():
     """The matrix engine exists for complex64 tiles of 2^14 with 32 registers
-    per lane; other requests are refused on the host, and the plan (and so
-    the op trace) is the butterfly plan's."""
+    per lane and whole-tile exchanges; other requests are refused on the
+    host, and the plan (and so the op trace) is the butterfly plan's with
+    whole-tile exchanges."""
     J = workloads.ladder(9)
     o = spq.Options(engine=1)
     info = spq.spin_describe_plan(spq.SPIN_C64, 18, J, 0.05, 10, 0, o)
     assert info["engine"] == 1 and info["reg_bits"] == 5 and info["tile_bits"] == 14
+    assert info["exchange"] == 1
     t1 = spq.spin_plan_trace(spq.SPIN_C64, 18, J, 0.05, 10, 0, o)
-    t0 = spq.spin_plan_trace(spq.SPIN_C64, 18, J, 0.05, 10, 0)
+    t0 = spq.spin_plan_trace(spq.SPIN_C64, 18, J, 0.05, 10, 0, spq.Options(exchange=1))
     assert np.array_equal(t0, t1)
+    with pytest.raises(spq.SpinError) as e:
+        spq.spin_describe_plan(spq.SPIN_C64, 18, J, 0.05, 10, 0, spq.Options(engine=1, exchange=2))
+    assert e.value.code == spq.SPIN_EUNSUPPORTED
+    with pytest.raises(spq.SpinError) as e:
+        spq.spin_describe_plan(spq.SPIN_C64, 18, J, 0.05, 10, 0, spq.Options(exchange=3))
+    assert e.value.code == spq.SPIN_EINVAL
     for prec, kw, code in [(spq.SPIN_C128, {}, spq.SPIN_EUNSUPPORTED),
                            (spq.SPIN_C64, {"tile_bits": 13}, spq.SPIN_EUNSUPPORTED),
                            (spq.SPIN_C64, {"reg_bits": 4}, spq.SPIN_EUNSUPPORTED)]:
@@ -255,3 +264,69 @@ def test_profile_plan_encodes_with_many_steps_per_pass():
     for prec, M, steps in [(spq.SPIN_C64, 28, 4), (spq.SPIN_C128, 24, 50), (spq.SPIN_C64, 34, 4)]:
         info = spq.spin_describe_plan(prec, M, [(0, M - 1, 0.2, 0.9)], 0.1, steps, spq.SPIN_ALL_SITES)
         assert info["path"] == 2
+
+
+# ------------------------------------------------------------------ exchanges
+_XCHECK = None
+
+
+def _exchange_check_binary(tmp_path_factory):
+    """Builds tests/host_checks/exchange_check.cpp against the planner."""
+    global _XCHECK
+    if _XCHECK is None:
+        out = str(tmp_path_factory.mktemp("xcheck") / "exchange_check")
+        subprocess.check_call(["g++", "-O2", "-std=c++17",
+                               os.path.join(ROOT, "tests", "host_checks", "exchange_check.cpp"),
+                               os.path.join(ROOT, "paper_0710_3747_amd", "csrc", "planner.cpp"),
+                               "-o", out])
+        _XCHECK = out
+    return _XCHECK
+
+
+def _run_exchange_check(binary, M, J, prec, k, r, c, steps, obs=0, plant=0, half=0):
+    inp = f"{M} {prec} {k} {r} {c} {steps} {obs} {plant} {half}\n" + "".join(
+        f"{i} {j} {a!r} {b!r}\n" for i, j, a, b in J)
+    p = subprocess.run([binary], input=inp, capture_output=True, text=True, timeout=600)
+    return p.returncode, p.stdout
+
+
+EXCHANGE_CASES = [
+    # name, M, couplings, prec, k, r, c, steps, half-tile exchanges
+    ("ladder2x15-c64-k14r5c4-half", 30, workloads.ladder(15), 1, 14, 5, 4, 1000, 1),
+    # 2-stage passes whose only exchange stays in each wave (their first
+    # exchange must carry the workgroup barrier)
+    ("ladder2x15-c64-k14r5c5-half-3steps", 30, workloads.ladder(15), 1, 14, 5, 5, 3, 1),
+    ("ladder2x15-c64-k14r5c4", 30, workloads.ladder(15), 1, 14, 5, 4, 100, 0),
+    ("ladder2x15-c64-k14r5c6", 30, workloads.ladder(15), 1, 14, 5, 6, 100, 0),
+    ("ladder2x15-c64-k14r6c4-half", 30, workloads.ladder(15), 1, 14, 6, 4, 100, 1),
+    ("ladder2x15-c64-k14r4c4", 30, workloads.ladder(15), 1, 14, 4, 4, 100, 0),
+    ("ladder2x15-c128-k13r4c4-half", 30, workloads.ladder(15), 2, 13, 4, 4, 100, 1),
+    ("ladder2x15-c128-k13r5c4-half", 30, workloads.ladder(15), 2, 13, 5, 4, 100, 1),
+    ("star28-c64-k14r5c6-half", 28, workloads.star(28, 33), 1, 14, 5, 6, 12, 1),
+    ("star20-c64-k14r5c4", 20, workloads.star(20, 2000), 1, 14, 5, 4, 60, 0),
+    ("ladder2x9-c128-k12r3c4", 18, workloads.ladder(9), 2, 12, 3, 4, 30, 0),
+]
+
+
+@pytest.mark.parametrize("case", EXCHANGE_CASES, ids=[c[0] for c in EXCHANGE_CASES])
+def test_wave_local_exchanges_stay_in_their_wave(case, tmp_path_factory):
+    """Every stage exchange the tables mark as wave-local (no workgroup
+    barrier) moves amplitudes only within each wave, tile boundaries
+    without a barrier keep every wave's LDS slots, and passes with no
+    barrier at all store exactly the offsets each wave loaded -- by
+    emulating the kernel's LDS and global address arithmetic on the host.
+    Half-tile passes also keep their split position on the top register bit
+    with no LDS image, and map each half one-to-one onto the buffer."""
+    name, M, J, prec, k, r, c, steps, half = case
+    rc, out = _run_exchange_check(_exchange_check_binary(tmp_path_factory), M, J, prec, k, r, c, steps,
+                                  half=half)
+    assert rc == 0, out
+    assert "failures 0" in out
+
+
+def test_exchange_check_reports_a_planted_cross_wave_exchange(tmp_path_factory):
+    """The same check reports a failure when every exchange is (wrongly)
+    marked wave-local."""
+    rc, out = _run_exchange_check(_exchange_check_binary(tmp_path_factory), 30, workloads.ladder(15), 1,
+                                  14, 5, 4, 40, plant=1)
+    assert rc == 1 and "moves amplitudes between waves" in out
