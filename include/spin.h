@@ -158,6 +158,30 @@ int spin_trotter_evolve_ex(void *psi, int32_t prec, int32_t M, const spin_coupli
                            void *stream);
 
 /*
+ * spin_trotter_evolve_noalloc -- spin_trotter_evolve_ex for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same arguments, results and
+ * stream semantics; it calls no device allocation.
+ *  - The plan for these arguments must already be cached on the current
+ *    device (spin_prepare_plan with the same prec, M, J, K, dt, n_steps,
+ *    observed_site and options); otherwise SPIN_EUNSUPPORTED, nothing
+ *    enqueued.
+ *  - The per-workgroup partial sums of the observable live in a fixed
+ *    device array of SPIN_NOALLOC_SCRATCH_BYTES per GPU, held by the library
+ *    until the process ends and shared by every such call on that GPU: calls
+ *    that overlap on one GPU (other streams, other threads) race.  The array
+ *    needs no clearing between calls; a call that needs more step slots than
+ *    it holds for its workgroups gets SPIN_EUNSUPPORTED.
+ *  - use_graph is refused (SPIN_EUNSUPPORTED); the unfused schedule
+ *    (schedule = 1) is served.
+ */
+#define SPIN_NOALLOC_SCRATCH_BYTES (1u << 20)
+int spin_trotter_evolve_noalloc(void *psi, int32_t prec, int32_t M, const spin_coupling *J,
+                                int32_t K, double dt, int64_t n_steps, int32_t observed_site,
+                                double *P_dev, double *N_dev, const spin_options *opt,
+                                void *stream);
+
+/*
  * observed_site value that selects the all-site profile's plan in
  * spin_prepare_plan, spin_describe_plan and spin_plan_trace.
  */

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "SPIN_C64", "SPIN_C128", "SpinError", "library_path", "load_library",
     "spin_init_random_phase", "spin_init_product", "spin_trotter_evolve", "spin_trotter_evolve_ex",
-    "spin_trotter_evolve_profile", "SPIN_ALL_SITES",
+    "spin_trotter_evolve_profile", "spin_trotter_evolve_noalloc", "SPIN_ALL_SITES",
     "spin_local_polarization", "spin_local_polarization_ex", "spin_trotter_evolve_batch",
     "spin_batch_status", "spin_describe_plan",
     "spin_plan_trace", "spin_last_error", "spin_release_caches", "spin_version",
@@ -105,6 +105,7 @@ def load_library():
     lib.spin_trotter_evolve.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, vp]
     lib.spin_trotter_evolve_ex.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, op, vp]
     lib.spin_trotter_evolve_profile.argtypes = [vp, i32, i32, cp, i32, dbl, i64, vp, vp, op, vp]
+    lib.spin_trotter_evolve_noalloc.argtypes = [vp, i32, i32, cp, i32, dbl, i64, i32, vp, vp, op, vp]
     lib.spin_local_polarization.argtypes = [vp, i32, i32, i32, vp, vp]
     lib.spin_local_polarization_ex.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     lib.spin_batch_status.argtypes = [vp]
@@ -123,7 +124,7 @@ def load_library():
     lib.spin_version.restype = ctypes.c_char_p
     lib.spin_release_caches.restype = None
     for name in ("spin_init_random_phase", "spin_init_product", "spin_trotter_evolve",
-                 "spin_trotter_evolve_ex",
+                 "spin_trotter_evolve_ex", "spin_trotter_evolve_noalloc",
                  "spin_trotter_evolve_profile",
                  "spin_local_polarization", "spin_local_polarization_ex",
                  "spin_trotter_evolve_batch", "spin_batch_status", "spin_prepare_plan",
@@ -215,6 +216,19 @@ def spin_trotter_evolve_ex(psi, M: int, couplings, dt: float, n_steps: int, obse
                                       _f64(P, n_steps + 1, "P"), _f64(N, n_steps + 1, "N"),
                                       ctypes.byref(options) if options is not None else None,
                                       _stream(stream)))
+
+
+def spin_trotter_evolve_noalloc(psi, M: int, couplings, dt: float, n_steps: int, observed_site: int,
+                                P, N=None, options: Optional[Options] = None, stream=None) -> None:
+    """spin_trotter_evolve_ex without device allocation (plan prepared first
+    with spin_prepare_plan; see include/spin.h)."""
+    lib = load_library()
+    p, prec = _state(psi, M)
+    arr, K = _couplings(couplings)
+    _check(lib.spin_trotter_evolve_noalloc(p, prec, M, arr, K, float(dt), int(n_steps), observed_site,
+                                           _f64(P, n_steps + 1, "P"), _f64(N, n_steps + 1, "N"),
+                                           ctypes.byref(options) if options is not None else None,
+                                           _stream(stream)))
 
 
 def spin_trotter_evolve(psi, M: int, couplings, dt: float, n_steps: int, observed_site: int,

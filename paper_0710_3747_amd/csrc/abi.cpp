@@ -275,7 +275,7 @@ static int build_plan(const PlanKey& key, const std::vector<Coupling>& J, const 
 
 int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t n_steps,
              int observed, const spin_options* opt, bool profile,
-             std::shared_ptr<DevicePlan>* out, Shape* shape_out) {
+             std::shared_ptr<DevicePlan>* out, Shape* shape_out, bool lookup_only = false) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     Shape sh = choose_shape(prec, M, opt);
@@ -305,6 +305,9 @@ int get_plan(int prec, int M, const std::vector<Coupling>& J, double dt, int64_t
             return SPIN_OK;
         }
     }
+    if (lookup_only)
+        return fail(SPIN_EUNSUPPORTED, "no prepared plan for these arguments: call spin_prepare_plan with "
+                                       "the same arguments first (this entry point allocates nothing)");
     std::shared_ptr<DevicePlan> dp;
     int rc = prec == SPIN_C64 ? build_plan<float>(key, J, sh, &dp) : build_plan<double>(key, J, sh, &dp);
     if (rc) return rc;
@@ -388,11 +391,16 @@ static void release_graphs() {
 template <typename T>
 static int evolve_naive(void* psi, int M, const std::vector<Coupling>& J, double dt,
                         int64_t n_steps, int observed, double* P, double* N, bool profile,
-                        hipStream_t st) {
+                        const Workspace* ws, hipStream_t st) {
     const int nblk = 1024;
     void* scratch = nullptr;
-    int rc = scratch_get(st, size_t(nblk) * 2 * sizeof(double), &scratch);
-    if (rc) return rc;
+    int rc;
+    if (ws) {
+        if (ws->doubles < size_t(nblk) * 2) return fail(SPIN_EUNSUPPORTED, "workspace too small");
+        scratch = ws->ptr;
+    } else if ((rc = scratch_get(st, size_t(nblk) * 2 * sizeof(double), &scratch))) {
+        return rc;
+    }
     double* part = static_cast<double*>(scratch);
     // With `profile`, P holds M values per step (row k = every site after k
     // steps) and N is taken with the observed site's value.
@@ -505,13 +513,16 @@ static int evolve_profile(void* psi, int M, const DevicePlan& dp, int64_t n_step
 template <typename T>
 static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double dt,
                         int64_t n_steps, int observed, double* P, double* N,
-                        const spin_options* opt, bool profile, hipStream_t st) {
+                        const spin_options* opt, bool profile, const Workspace* ws, hipStream_t st) {
     std::shared_ptr<DevicePlan> dp;
     Shape sh;
-    int rc = get_plan(sizeof(T) == 4 ? SPIN_C64 : SPIN_C128, M, J, dt, n_steps, observed, opt,
-                      profile, &dp, &sh);
-    if (rc) return rc;
     const bool graph = opt && opt->use_graph;
+    if (ws && (graph || profile))
+        return fail(SPIN_EUNSUPPORTED, "the allocation-free call supports neither graph capture nor the "
+                                       "all-site profile");
+    int rc = get_plan(sizeof(T) == 4 ? SPIN_C64 : SPIN_C128, M, J, dt, n_steps, observed, opt,
+                      profile, &dp, &sh, ws != nullptr);
+    if (rc) return rc;
     if (profile) return evolve_profile<T>(psi, M, *dp, n_steps, P, N, graph, st);
     if (dp->resident) {
         ResidentJob job{};
@@ -530,10 +541,24 @@ static int evolve_fused(void* psi, int M, const std::vector<Coupling>& J, double
         return SPIN_OK;
     }
     const int64_t total = n_steps + 1;
-    const int ch = int(std::min<int64_t>(total, 1024));
+    int ch = int(std::min<int64_t>(total, 1024));
     void* scratch = nullptr;
-    rc = scratch_get(st, size_t(ch) * dp->nwg * 2 * sizeof(double), &scratch);
-    if (rc) return rc;
+    if (ws) {
+        // as many step slots as the workspace holds; a launch measures at
+        // most kMaxMeas consecutive steps and the slots are reduced once half
+        // of them are in use, so 2 * kMaxMeas slots suffice
+        const int64_t fit = int64_t(ws->doubles / (size_t(2) * size_t(dp->nwg)));
+        ch = int(std::min<int64_t>(ch, fit));
+        if (ch < std::min<int64_t>(total, 2 * kMaxMeas)) {
+            std::ostringstream os;
+            os << "workspace too small: " << dp->nwg << " workgroups need " << 2 * kMaxMeas * 2 * dp->nwg
+               << " doubles, the allocation-free workspace holds " << ws->doubles;
+            return fail(SPIN_EUNSUPPORTED, os.str());
+        }
+        scratch = ws->ptr;
+    } else if ((rc = scratch_get(st, size_t(ch) * dp->nwg * 2 * sizeof(double), &scratch))) {
+        return rc;
+    }
     double* part = static_cast<double*>(scratch);
     auto enqueue = [&](hipStream_t st) -> int {
         int64_t measured = 0, reduced = 0;
@@ -636,7 +661,8 @@ namespace spinqp {
 // spin_trotter_evolve_profile (every site; the norm rides on site 0).
 static int evolve_entry(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
                         double dt, int64_t n_steps, int32_t observed_site, bool profile,
-                        double* P_dev, double* N_dev, const spin_options* opt, void* stream) {
+                        double* P_dev, double* N_dev, const spin_options* opt, void* stream,
+                        const Workspace* ws = nullptr) {
     try {
         int rc = validate_common(psi, prec, M);
         if (rc) return rc;
@@ -657,12 +683,13 @@ static int evolve_entry(void* psi, int32_t prec, int32_t M, const spin_coupling*
         const bool naive = opt && opt->schedule == 1;
         if (naive) {
             rc = prec == SPIN_C64
-                     ? evolve_naive<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, profile, st)
-                     : evolve_naive<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, profile, st);
+                     ? evolve_naive<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, profile, ws, st)
+                     : evolve_naive<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, profile, ws, st);
         } else {
             rc = prec == SPIN_C64
-                     ? evolve_fused<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, profile, st)
-                     : evolve_fused<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, profile, st);
+                     ? evolve_fused<float>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, profile, ws, st)
+                     : evolve_fused<double>(psi, M, Jv, dt, n_steps, observed_site, P_dev, N_dev, opt, profile, ws,
+                                            st);
         }
         if (rc == SPIN_OK) g_err.clear();
         return rc;
@@ -670,6 +697,16 @@ static int evolve_entry(void* psi, int32_t prec, int32_t M, const spin_coupling*
         return fail(SPIN_EUNSUPPORTED, std::string("internal error: ") + e.what());
     }
 }
+int evolve_with_workspace(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                          double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
+                          double* N_dev, const spin_options* opt, void* stream, double* ws,
+                          size_t ws_doubles) {
+    if (!ws) return fail(SPIN_EINVAL, "workspace is NULL");
+    const Workspace w{ws, ws_doubles};
+    return evolve_entry(psi, prec, M, J, K, dt, n_steps, observed_site, false, P_dev, N_dev, opt,
+                        stream, &w);
+}
+
 }  // namespace spinqp
 
 extern "C" {

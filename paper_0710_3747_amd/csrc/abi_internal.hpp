@@ -1,6 +1,7 @@
 // abi_internal.hpp -- helpers shared by the C-ABI translation units.
 #pragma once
 
+#include <cstddef>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,21 @@ struct Shape {
     bool valid = true;  // a pass kernel exists for (r, nt, engine)
 };
 Shape choose_shape(int prec, int M, const spin_options* opt);
+
+// Caller-provided device workspace for the per-workgroup partial sums (the
+// allocation-free entry point); with one, plans must already be cached.
+struct Workspace {
+    double* ptr;
+    size_t doubles;
+};
+// spin_trotter_evolve_ex with partial sums in `ws` (ws_doubles doubles):
+// no device allocation; SPIN_EUNSUPPORTED when the plan is not cached, when
+// graph capture or the all-site profile is asked for, or when `ws` is too
+// small for the plan's workgroups.
+int evolve_with_workspace(void* psi, int32_t prec, int32_t M, const spin_coupling* J, int32_t K,
+                          double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
+                          double* N_dev, const spin_options* opt, void* stream, double* ws,
+                          size_t ws_doubles);
 void release_batch_caches();
 void release_tune_cache();
 
