@@ -140,7 +140,7 @@ def other_workload(name):
                     observed=0, polarized=0)
     if name == "star_28":
         c = workloads.STAR_M28
-        return dict(name="star_28_xy", M=c["M"], J=workloads.star(c["M"], c["coupling_seed"]),
+        return dict(name="star_28_xy_blocks", M=c["M"], J=workloads.star_m28(),
                     dt=c["dt"], steps=c["n_steps"], seed=c["seed"], observed=0, polarized=0)
     raise ValueError(name)
 
@@ -201,12 +201,12 @@ def run_batch(spq, torch, prec=None, reps=2):
 
 
 def run_star(spq, torch, steps, warmup):
-    """The all-to-all star M = 28 (378 couplings) in both precisions, at
-    the complex64 shape the autotuner picks for it (k 14, r 5, c 6) and the
-    complex128 default."""
+    """The all-to-all star M = 28 (378 couplings, block order) in both
+    precisions, at the complex64 shape with 64 amplitudes per lane (k 14,
+    r 6, c 4, half-tile exchanges) and the complex128 default."""
     import numpy as np
     w = other_workload("star_28")
-    o = spq.Options(tile_bits=14, reg_bits=5, coalesce_bits=6)
+    o = spq.Options(tile_bits=14, reg_bits=6, coalesce_bits=4)
     r32 = run_path(spq, torch, w, spq.SPIN_C64, steps, warmup, o)
     r64 = run_path(spq, torch, w, spq.SPIN_C128, steps, warmup, None)
     s32 = summarize(r32, w, steps, 8)
@@ -534,7 +534,8 @@ def main():
         # 32 x 32 complex matrix) against the VALU butterflies, same shape
         import numpy as np
         n = min(args.engine_steps, steps)
-        base = dict(tile_bits=14, reg_bits=5, coalesce_bits=5)
+        # both on whole-tile exchanges (the matrix engine's only form)
+        base = dict(tile_bits=14, reg_bits=5, coalesce_bits=5, exchange=1)
         print(f"[bench] engine comparison, {n} steps", file=sys.stderr, flush=True)
         rb = run_path(spq, torch, w, spq.SPIN_C64, n, 2, spq.Options(**base))
         rm = run_path(spq, torch, w, spq.SPIN_C64, n, 2, spq.Options(engine=1, **base))

@@ -167,19 +167,23 @@ static int upload_tables(const DevTables<T>& tb, DevicePlan* dp) {
 }
 
 // Launch shape: tile bits k = r + log2(nt).  Defaults: complex64 tiles of
-// 2^14 amplitudes (128 KiB of LDS), complex128 tiles of 2^13 (128 KiB).
+// 2^14 amplitudes, complex128 tiles of 2^13 (128 KiB either way), exchanged
+// through LDS in halves where a kernel exists (two workgroups per CU).
 Shape choose_shape(int prec, int M, const spin_options* opt) {
     Shape s;
     const bool f32 = prec == SPIN_C64;
+    const int ex = opt ? opt->exchange : 0;
     int k = f32 ? 14 : 13;
-    s.r = f32 ? 5 : 4;
+    // complex128 tiles: 16 amplitudes per lane with half-tile exchanges
+    // (two 256-lane workgroups per CU), 8 with whole tiles
+    s.r = (f32 || ex != 1) ? 5 : 4;
     // 4 low address bits in every tile: 128-byte runs of complex64 (fewer
     // passes than 256-byte runs, which outweighs the slower sweep on the
     // ladders), 256-byte runs of complex128
     s.c = 4;
     if (opt && opt->tile_bits > 0) {
         k = opt->tile_bits;
-        s.r = f32 ? (k <= 12 ? 4 : 5) : 4;
+        s.r = f32 ? (k <= 12 ? 4 : 5) : (ex != 1 && k == 13 ? 5 : 4);
     }
     if (opt && opt->reg_bits > 0) s.r = opt->reg_bits;
     if (opt && opt->coalesce_bits > 0) s.c = opt->coalesce_bits;
@@ -187,7 +191,6 @@ Shape choose_shape(int prec, int M, const spin_options* opt) {
     s.nt = (k - s.r >= 0 && k - s.r < 16) ? (1 << (k - s.r)) : 0;
     s.k = k;
     s.engine = opt ? opt->engine : 0;
-    const int ex = opt ? opt->exchange : 0;
     const bool half_ok = s.engine == 0 && pass_half_exists(f32, s.r, s.nt);
     s.half = ex == 2 || (ex == 0 && half_ok);
     s.valid = s.half ? half_ok : pass_shape_exists(f32, s.r, s.nt, s.engine);

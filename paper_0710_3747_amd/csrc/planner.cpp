@@ -999,12 +999,16 @@ StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, in
     // planning time small against the run.
     // A window of 5 steps pays when few low bits are pinned (c = 4 on the
     // ladders: 6 % fewer passes); it is tried with policy 2 only.
+    // Variants are ranked on whole-tile staging (cheaper to plan); the chosen
+    // plan is staged again below, with the split positions of half-tile
+    // exchanges when asked for.
     std::vector<PassParams> vs;
     for (int rotate : {0, 3, 6, 9, 12, 15})
         for (int window : {3, 4, 5})
             for (int policy : {2, 1}) {
                 if (window == 5 && policy != 2) continue;
                 PassParams v = pp;
+                v.half = false;
                 v.window = window;
                 v.low_policy = policy;
                 v.rotate = rotate % std::max(M, 1);
@@ -1023,16 +1027,19 @@ StreamPlan plan_stream_best(int M, const std::vector<Coupling>& J, double dt, in
         }
     }
     // The chosen plan's register stages again, with a beam search (too slow
-    // for every variant); a pass keeps whichever staging is shorter.
-    if (nv > 1)
+    // for every variant); a pass keeps whichever staging is shorter.  For
+    // half-tile exchanges every pass is staged again around its split
+    // position.
+    if (pp.half) {
+        for (HostPass& hp : best.passes)
+            plan_stages_coalesced(hp, std::min(pp.r, int(hp.sites.size())), pp.c, nv > 1 ? 32 : 1, true);
+    } else if (nv > 1) {
         for (HostPass& hp : best.passes) {
             HostPass alt = hp;
-            plan_stages_coalesced(alt, std::min(pp.r, int(alt.sites.size())), pp.c, 32, pp.half);
-            if (alt.stages.size() < hp.stages.size()) {
-                hp.stages = std::move(alt.stages);
-                hp.split = alt.split;
-            }
+            plan_stages_coalesced(alt, std::min(pp.r, int(alt.sites.size())), pp.c, 32);
+            if (alt.stages.size() < hp.stages.size()) hp.stages = std::move(alt.stages);
         }
+    }
     return best;
 }
 

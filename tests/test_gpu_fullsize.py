@@ -158,11 +158,12 @@ def test_time_reversal_echo_M30():
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_star_28_sectors(prec):
-    """Star M = 28 (378 couplings, J_0j ~ N(0,1), J_ij ~ N(0, 0.1)),
-    dt = 0.02: sectors with <= 2 spins down after 12 steps."""
+    """Star M = 28 (378 couplings, J_0j ~ N(0,1), J_ij ~ N(0, 0.1), in the
+    workload's block order), dt = 0.02: sectors with <= 2 spins down after
+    12 steps."""
     cfg = workloads.STAR_M28
     M = cfg["M"]
-    J = workloads.star(M, cfg["coupling_seed"])
+    J = workloads.star_m28()
     note("star 28", prec)
     P, N, _, t = gpu_evolve(prec, M, J, cfg["dt"], 12, 0, seed=cfg["seed"], keep_state=False)
     sector_check(t, M, J, cfg["dt"], 12, cfg["seed"], prec, [0, 1, 2, 27])

@@ -112,15 +112,27 @@ def ladder30():
     orc.release()
 
 
-# the default shapes, then the complex64 shapes the autotuner chooses between
-# for the benchmark (tile bits, register bits, coalescing bits)
-LADDER_SHAPES = [(C128, None), (C64, None), (C64, (14, 5, 5)), (C64, (14, 5, 6)), (C64, (14, 4, 4))]
-LADDER_IDS = [("c64" if p == C64 else "c128") + ("-default" if s is None else "-k%d-r%d-c%d" % s)
-              for p, s in LADDER_SHAPES]
+# the default shapes (half-tile exchanges), then shapes the autotuner chooses
+# between for the benchmark (tile bits, register bits, coalescing bits, and
+# exchange 1 = whole tiles where given)
+LADDER_SHAPES = [(C128, None), (C64, None), (C64, (14, 5, 5)), (C64, (14, 5, 6)), (C64, (14, 6, 4)),
+                 (C64, (14, 5, 4, 1)), (C64, (14, 4, 4, 1)), (C128, (13, 4, 4, 1))]
+
+
+def _shape_id(p, s):
+    name = "c64" if p == C64 else "c128"
+    if s is None:
+        return name + "-default"
+    return name + "-k%d-r%d-c%d" % s[:3] + ("-whole" if len(s) > 3 and s[3] == 1 else "")
+
+
+LADDER_IDS = [_shape_id(p, s) for p, s in LADDER_SHAPES]
 
 
 def _opts(shape):
-    return None if shape is None else dict(zip(("tile_bits", "reg_bits", "coalesce_bits"), shape))
+    if shape is None:
+        return None
+    return dict(zip(("tile_bits", "reg_bits", "coalesce_bits", "exchange"), shape))
 
 
 @pytest.mark.timeout(600)
@@ -141,18 +153,18 @@ def test_ladder_2x15_twenty_steps_whole_state(ladder30, prec):
 @pytest.fixture(scope="module")
 def star28():
     cfg = workloads.STAR_M28
-    orc = OracleRun(cfg["M"], workloads.star(cfg["M"], cfg["coupling_seed"]), cfg["dt"], cfg["seed"])
+    orc = OracleRun(cfg["M"], workloads.star_m28(), cfg["dt"], cfg["seed"])
     yield orc
     orc.release()
 
 
-STAR_SHAPES = [(C128, None), (C64, None), (C64, (14, 5, 6))]
-STAR_IDS = [("c64" if p == C64 else "c128") + ("-default" if s is None else "-k%d-r%d-c%d" % s)
-            for p, s in STAR_SHAPES]
+STAR_SHAPES = [(C128, None), (C64, None), (C64, (14, 6, 4))]
+STAR_IDS = [_shape_id(p, s) for p, s in STAR_SHAPES]
 
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec,shape", STAR_SHAPES, ids=STAR_IDS)
 def test_star_28_two_steps_whole_state(star28, prec, shape):
-    """Star M = 28 (378 couplings), 2 steps: every P[k], N[k] and amplitude."""
+    """Star M = 28 (378 couplings in the workload's block order), 2 steps:
+    every P[k], N[k] and amplitude."""
     check_against(star28, prec, 2, _opts(shape))
