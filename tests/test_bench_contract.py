@@ -25,7 +25,7 @@ def counters_current():
     return h.hexdigest()[:16] == t["kernel_source_sha256_16"]
 
 
-@pytest.mark.parametrize("prec,k,r,c,x", [("c64", 14, 5, 4, 2), ("c64", 14, 5, 4, 1), ("c128", 13, 4, 4, 2)])
+@pytest.mark.parametrize("prec,k,r,c,x", [("c64", 14, 6, 4, 2), ("c64", 14, 5, 4, 2), ("c128", 13, 5, 4, 2)])
 def test_measured_traffic_per_launch_shape(prec, k, r, c, x):
     if not counters_current():
         pytest.skip("kernel source changed since the HBM counters were taken (bench reports null)")
@@ -34,7 +34,7 @@ def test_measured_traffic_per_launch_shape(prec, k, r, c, x):
     alg = 2 * 2 ** 30 * (8 if prec == "c64" else 16)
     assert t is not None, key
     # one read and one write sweep per launch, within a few per cent
-    assert alg <= t < 1.03 * alg
+    assert 0.999 * alg <= t < 1.03 * alg
 
 
 def test_unmeasured_shape_reports_no_traffic():
