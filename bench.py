@@ -222,51 +222,75 @@ def run_star(spq, torch, steps, warmup):
             "err_P_fp32_vs_fp64": float(np.abs(r32["P"] - r64["P"]).max())}
 
 
-def run_ensemble(spq, torch, L=7, steps=100, dt=0.05, draws=256):
-    """The method's own speed-up: the 2^(M-1) basis-state members of the
-    ensemble (Eq. (1)) evolved in one batched launch, against one
-    random-phase state (Eq. (2)) and a batch of independent phase draws."""
+def run_ensemble(spq, torch, dt=0.05, draws=256, work_gib=32):
+    """The method's own speed-up (Eq. (1) against Eq. (2)): the 2^(M-1)
+    basis-state members of the ensemble evolved one by one on the GPU
+    (spin_ensemble_evolve, member average on the device), against one
+    random-phase state of the same ladder; at M = 14 also the members as
+    one batched launch and the mean of independent phase draws (Eq. (4))."""
     import numpy as np
     import workloads
-    M = 2 * L
-    J = workloads.ladder(L)
-    xs = [x for x in range(2 ** M) if not (x & 1)]
+    out = []
+    for L, steps in ((7, 100), (9, 50)):
+        M = 2 * L
+        J = workloads.ladder(L)
+        D = 2 ** (M - 1)
+        members_per_evolution = min(D, (work_gib << 30) // (8 * 2 ** M))
+        work = torch.empty(members_per_evolution * 2 ** M, dtype=torch.complex64, device="cuda")
+        Pe = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+        t_ens = None
+        for rep in range(2):      # the first call plans
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            spq.spin_ensemble_evolve(work, M, J, dt, steps, 0, 0, Pe)
+            torch.cuda.synchronize()
+            t_ens = time.perf_counter() - t0
+        del work
+        torch.cuda.empty_cache()
+        Pbar = Pe.cpu().numpy()
+        psi = torch.empty(2 ** M, dtype=torch.complex64, device="cuda")
+        P1 = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+        for rep in range(2):
+            spq.spin_init_random_phase(psi, M, 0, 7)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            spq.spin_trotter_evolve(psi, M, J, dt, steps, 0, P1)
+            torch.cuda.synchronize()
+            t_one = time.perf_counter() - t0
+        n_factors = 2 * len(J)
+        r = {"workload": f"ladder_2x{L}_xy", "M": M, "steps": steps, "dt": dt,
+             "ensemble_members": D, "members_per_evolution": members_per_evolution,
+             "ensemble_seconds": t_ens,
+             "ensemble_amplitude_updates_per_s": D * 2.0 ** M * n_factors * steps / t_ens,
+             "one_random_phase_seconds": t_one,
+             "ensemble_over_one_state": t_ens / t_one,
+             "max_dP_one_state_vs_ensemble": float(np.abs(P1.cpu().numpy() - Pbar).max()),
+             "bound_std_one_state": 2.0 * 2.0 ** (-(M - 1) / 2)}
+        if L == 7:
+            def batch(seeds, init):
+                big = torch.empty(len(seeds), 2 ** M, dtype=torch.complex64, device="cuda")
+                Pb = torch.zeros(len(seeds), steps + 1, dtype=torch.float64, device="cuda")
+                probs = [dict(psi=big[i], M=M, couplings=J, observed_site=0, polarized_site=0,
+                              seed=int(x), P=Pb[i]) for i, x in enumerate(seeds)]
+                spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)   # plans
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                if spq.spin_batch_status() != 0:
+                    raise RuntimeError("ensemble batch: " + spq.spin_last_error())
+                return sec, Pb.cpu().numpy()
 
-    def batch(seeds, init):
-        big = torch.empty(len(seeds), 2 ** M, dtype=torch.complex64, device="cuda")
-        Pb = torch.zeros(len(seeds), steps + 1, dtype=torch.float64, device="cuda")
-        probs = [dict(psi=big[i], M=M, couplings=J, observed_site=0, polarized_site=0, seed=int(x),
-                      P=Pb[i]) for i, x in enumerate(seeds)]
-        spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)   # plans, warms
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        spq.spin_trotter_evolve_batch(probs, spq.SPIN_C64, dt, steps, init=init)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        if spq.spin_batch_status() != 0:
-            raise RuntimeError("ensemble batch: " + spq.spin_last_error())
-        return sec, Pb.cpu().numpy()
-
-    t_ens, P_ens = batch(xs, spq.SPIN_INIT_BASIS)
-    t_draws, P_draws = batch(list(range(draws)), spq.SPIN_INIT_RANDOM_PHASE)
-    psi = torch.empty(2 ** M, dtype=torch.complex64, device="cuda")
-    P1 = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
-    for rep in range(2):
-        spq.spin_init_random_phase(psi, M, 0, 7)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        spq.spin_trotter_evolve(psi, M, J, dt, steps, 0, P1)
-        torch.cuda.synchronize()
-        t_one = time.perf_counter() - t0
-    Pbar = P_ens.mean(0)
-    return {"workload": f"ladder_2x{L}_xy", "M": M, "steps": steps, "dt": dt,
-            "ensemble_members": len(xs), "ensemble_seconds": t_ens,
-            "one_random_phase_seconds": t_one,
-            "ensemble_over_one_state": t_ens / t_one,
-            "phase_draws": draws, "phase_draws_seconds": t_draws,
-            "max_dP_one_state_vs_ensemble": float(np.abs(P1.cpu().numpy() - Pbar).max()),
-            "max_dP_mean_of_draws_vs_ensemble": float(np.abs(P_draws.mean(0) - Pbar).max()),
-            "bound_std_one_state": 2.0 * 2.0 ** (-(M - 1) / 2)}
+            xs = [x for x in range(2 ** M) if not (x & 1)]
+            t_b, P_b = batch(xs, spq.SPIN_INIT_BASIS)
+            t_draws, P_draws = batch(list(range(draws)), spq.SPIN_INIT_RANDOM_PHASE)
+            r.update({"batched_members_seconds": t_b,
+                      "max_dP_batched_members_vs_ensemble": float(np.abs(P_b.mean(0) - Pbar).max()),
+                      "phase_draws": draws, "phase_draws_seconds": t_draws,
+                      "max_dP_mean_of_draws_vs_ensemble": float(np.abs(P_draws.mean(0) - Pbar).max())})
+        out.append(r)
+    return out
 
 
 def shape_key(prec_name, info):

@@ -282,6 +282,49 @@ int spin_trotter_evolve_batch(const spin_problem *probs, int32_t n, const spin_c
 int spin_batch_status(void *stream);
 
 /*
+ * spin_ensemble_evolve -- the ensemble average of Eq. (1) taken literally
+ * (section "Ensemble vs. pure entangled state"), the computation the
+ * random-phase state replaces: at infinite temperature with site
+ * `polarized_site` up, the ensemble is the 2^(M-1) Zeeman basis states |x>
+ * whose bit `polarized_site` is 0 (bit value 0 is spin up), each of weight
+ * 1/2^(M-1).  Every member is evolved on its own (n_steps Strang steps, as
+ * spin_trotter_evolve) and, for every step k, the mean over the members of
+ * their local polarization P = 2(W - 1/2) at `observed_site` is written to
+ * P_dev[k] (FP64).  Over the whole ensemble this is P^ens(t_k).
+ *   members : member r (0 <= r < 2^(M-1)) is the basis state whose bits on
+ *             the sites other than polarized_site are the bits of r, in
+ *             site order; the call averages members first_member ..
+ *             first_member + n_members - 1 (n_members >= 1; the whole
+ *             ensemble is 0, 2^(M-1)).
+ *   work, work_amplitudes : the caller's device buffer of work_amplitudes
+ *             amplitudes of `prec` (16-byte aligned, contents overwritten).
+ *             2^c members are evolved at once as one state of M + c sites
+ *             whose top c (uncoupled) sites hold the member index, with 2^c
+ *             the largest power of two that fits the buffer
+ *             (2^(M+c) <= work_amplitudes), does not exceed n_members
+ *             rounded up to a power of two, and keeps M + c within
+ *             SPIN_MAX_M_*; a buffer of 2^M amplitudes evolves one member at
+ *             a time.  Unused member slots of the last evolution hold zeros.
+ *   P_dev   : n_steps + 1 doubles (device), (1/n_members) sum_r P_r[k].
+ *   N_dev   : n_steps + 1 doubles (device), the mean norm, or NULL.
+ *   opt     : launch options of the (M + c)-site evolutions, as
+ *             spin_trotter_evolve_ex; may be NULL.
+ * The member sums are taken on the device in a fixed order (within one
+ * evolution by the fused observable's reduction, then evolutions in member
+ * order, then the division by n_members), so equal calls give equal bits.
+ * The work is enqueued on `stream` and the call returns without
+ * synchronising (the first call for new arguments plans synchronously).
+ * Errors: SPIN_EINVAL (prec, M, sites, member range, a null or misaligned
+ * work buffer, work_amplitudes < 2^M, null P_dev, couplings, dt, n_steps),
+ * SPIN_ENOMEM, SPIN_EHIP, SPIN_EUNSUPPORTED as spin_trotter_evolve_ex.
+ */
+int spin_ensemble_evolve(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,
+                         int64_t n_steps, int32_t polarized_site, int32_t observed_site,
+                         int64_t first_member, int64_t n_members, void *work,
+                         int64_t work_amplitudes, double *P_dev, double *N_dev,
+                         const spin_options *opt, void *stream);
+
+/*
  * spin_prepare_plan -- plans the call spin_trotter_evolve_ex would make with
  * the same arguments (prec, M, J, K, dt, n_steps, observed_site, opt) and
  * uploads the plan tables to the current device, where they stay cached

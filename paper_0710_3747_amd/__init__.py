@@ -21,7 +21,7 @@ __all__ = [
     "spin_init_random_phase", "spin_init_product", "spin_trotter_evolve", "spin_trotter_evolve_ex",
     "spin_trotter_evolve_profile", "spin_trotter_evolve_noalloc", "SPIN_ALL_SITES",
     "spin_local_polarization", "spin_local_polarization_ex", "spin_trotter_evolve_batch",
-    "spin_batch_status", "spin_describe_plan",
+    "spin_batch_status", "spin_ensemble_evolve", "spin_prepare_plan", "spin_describe_plan",
     "spin_plan_trace", "spin_last_error", "spin_release_caches", "spin_version",
     "Options", "Problem",
 ]
@@ -111,6 +111,8 @@ def load_library():
     lib.spin_batch_status.argtypes = [vp]
     lib.spin_trotter_evolve_batch.argtypes = [ctypes.POINTER(Problem), i32, cp, i64, i32, dbl,
                                               i64, i32, vp]
+    lib.spin_ensemble_evolve.argtypes = [i32, i32, cp, i32, dbl, i64, i32, i32, i64, i64, vp, i64,
+                                         vp, vp, op, vp]
     lib.spin_prepare_plan.argtypes = [i32, i32, cp, i32, dbl, i64, i32, op]
     lib.spin_autotune.argtypes = [i32, i32, cp, i32, dbl, i32, i64, ctypes.c_char_p, op,
                                   ctypes.POINTER(TuneResult), i32, ctypes.POINTER(ctypes.c_int32), vp]
@@ -127,7 +129,8 @@ def load_library():
                  "spin_trotter_evolve_ex", "spin_trotter_evolve_noalloc",
                  "spin_trotter_evolve_profile",
                  "spin_local_polarization", "spin_local_polarization_ex",
-                 "spin_trotter_evolve_batch", "spin_batch_status", "spin_prepare_plan",
+                 "spin_trotter_evolve_batch", "spin_batch_status", "spin_ensemble_evolve",
+                 "spin_prepare_plan",
                  "spin_describe_plan", "spin_plan_trace", "spin_autotune", "spin_tuned_options"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -308,6 +311,29 @@ def spin_trotter_evolve_batch(problems: Sequence[dict], prec: int, dt: float, n_
     carr, Ktot = _couplings(allJ)
     _check(lib.spin_trotter_evolve_batch(arr, len(problems), carr, Ktot, prec, float(dt),
                                          int(n_steps), int(init), _stream(stream)))
+
+
+def spin_ensemble_evolve(work, M: int, couplings, dt: float, n_steps: int, polarized_site: int,
+                         observed_site: int, P, N=None, first_member: int = 0,
+                         n_members: Optional[int] = None, options: Optional[Options] = None,
+                         stream=None) -> None:
+    """Mean polarization over basis-state members of the ensemble of Eq. (1)
+    (the whole ensemble by default); ``work`` is a contiguous complex64 or
+    complex128 device tensor of at least 2^M amplitudes that the call
+    overwrites (see include/spin.h)."""
+    lib = load_library()
+    if not work.is_cuda or not work.is_contiguous():
+        raise ValueError("work must be a contiguous device tensor")
+    prec = _prec_of(work)
+    if n_members is None:
+        n_members = 2 ** (M - 1) - first_member
+    arr, K = _couplings(couplings)
+    _check(lib.spin_ensemble_evolve(prec, M, arr, K, float(dt), int(n_steps), polarized_site,
+                                    observed_site, int(first_member), int(n_members),
+                                    ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                    _f64(P, n_steps + 1, "P"), _f64(N, n_steps + 1, "N"),
+                                    ctypes.byref(options) if options is not None else None,
+                                    _stream(stream)))
 
 
 def spin_prepare_plan(prec: int, M: int, couplings, dt: float, n_steps: int, observed_site: int,

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libspinqp.so")
-SOURCES = ["kernels.hip", "noalloc.hip", "planner.cpp", "abi.cpp", "batch.cpp", "autotune.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "planner.cpp", "abi.cpp", "batch.cpp", "autotune.cpp",
+           "ensemble.cpp"]
 ARCH = os.environ.get("SPINQP_ARCH", "gfx950")
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -75,20 +75,21 @@ int validate_couplings(int32_t M, const spin_coupling* J, int64_t K, std::vector
 }
 
 // ------------------------------------------------------------ workspaces
-// Device scratch for per-workgroup partial sums, grow-only, one per
-// (device, stream): calls on different streams never share one.
+// Device scratch, grow-only, one per (device, stream, slot): calls on
+// different streams never share one.  Slot 0 holds per-workgroup partial
+// sums, slot 1 the per-evolution member sums of spin_ensemble_evolve.
 struct Scratch {
     void* ptr = nullptr;
     size_t bytes = 0;
 };
 static std::mutex g_mu;
-static std::map<std::pair<int, hipStream_t>, Scratch> g_scratch;
+static std::map<std::tuple<int, hipStream_t, int>, Scratch> g_scratch;
 
-int scratch_get(hipStream_t st, size_t bytes, void** out) {
+int scratch_get_slot(hipStream_t st, int slot, size_t bytes, void** out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_mu);
-    Scratch& s = g_scratch[{dev, st}];
+    Scratch& s = g_scratch[std::make_tuple(dev, st, slot)];
     if (s.bytes < bytes) {
         if (s.ptr) {
             // previous work on this stream may still read it
@@ -107,6 +108,8 @@ int scratch_get(hipStream_t st, size_t bytes, void** out) {
     *out = s.ptr;
     return SPIN_OK;
 }
+
+int scratch_get(hipStream_t st, size_t bytes, void** out) { return scratch_get_slot(st, 0, bytes, out); }
 
 // ------------------------------------------------------------- plan cache
 struct PlanKey {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstddef>
+#include <hip/hip_runtime.h>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,10 @@ int evolve_with_workspace(void* psi, int32_t prec, int32_t M, const spin_couplin
                           double dt, int64_t n_steps, int32_t observed_site, double* P_dev,
                           double* N_dev, const spin_options* opt, void* stream, double* ws,
                           size_t ws_doubles);
+// Grow-only device scratch of at least `bytes`, one per (device, stream,
+// slot); slot 0 is the fused path's partial sums.  Growing it waits for
+// the stream.
+int scratch_get_slot(hipStream_t st, int slot, size_t bytes, void** out);
 void release_batch_caches();
 void release_tune_cache();
 

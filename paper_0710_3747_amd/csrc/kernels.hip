@@ -2,6 +2,9 @@
 //
 //  k_init        random-phase state (counter-based SplitMix64 phases)
 //  k_init_product  product state of M-1 random single-spin phases
+//  k_init_members  2^c basis-state members of the ensemble stacked as one
+//                state of M + c sites (member index on the top c bits)
+//  k_accumulate  member sums of consecutive evolutions, in order
 //  k_pass        one tiled sweep: a 2^k-amplitude tile per workgroup is
 //                staged through LDS; register stages apply the two-spin
 //                factors as three-shear rotations; observables are
@@ -127,6 +130,37 @@ __global__ __launch_bounds__(256) void k_init_product(typename CT<T>::c* __restr
         v.y = T(im);
         psi[x] = v;
     }
+}
+
+// Ensemble members stacked as one state of M + cbits sites: amplitude
+// x = (m << M) | y is 1 when m < count and y is the basis state of member
+// first + m (its bits spread over the sites other than `polarized`, whose
+// bit is 0: spin up), and 0 otherwise.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_members(typename CT<T>::c* __restrict__ psi, int M,
+                                                      int cbits, int polarized, uint64_t first,
+                                                      uint64_t count) {
+    const uint64_t dim = 1ull << (M + cbits);
+    const uint64_t ymask = (1ull << M) - 1;
+    const uint64_t low = (1ull << polarized) - 1;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t x = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < dim; x += stride) {
+        const uint64_t m = x >> M;
+        const uint64_t r = first + m;
+        const uint64_t basis = ((r & ~low) << 1) | (r & low);
+        typename CT<T>::c v;
+        v.x = T((m < count && (x & ymask) == basis) ? 1 : 0);
+        v.y = T(0);
+        psi[x] = v;
+    }
+}
+
+// acc[i] = (acc[i] + add[i]) * scale (add may be null), i < n.
+__global__ void k_accumulate(double* __restrict__ acc, const double* __restrict__ add, int64_t n,
+                             double scale) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        acc[i] = (acc[i] + (add ? add[i] : 0.0)) * scale;
 }
 
 // ---------------------------------------------------------- reductions
@@ -1206,6 +1240,22 @@ hipError_t launch_init_product(void* psi, int M, int n, uint64_t seed, hipStream
 }
 
 template <typename T>
+hipError_t launch_init_members(void* psi, int M, int cbits, int polarized, uint64_t first,
+                               uint64_t count, hipStream_t st) {
+    const int grid = grid_for(1ull << (M + cbits), 256, 1 << 16);
+    hipLaunchKernelGGL(k_init_members<T>, dim3(grid), dim3(256), 0, st,
+                       reinterpret_cast<typename CT<T>::c*>(psi), M, cbits, polarized, first, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double* acc, const double* add, int64_t n, double scale,
+                             hipStream_t st) {
+    const int grid = grid_for(uint64_t(n), 256, 1024);
+    hipLaunchKernelGGL(k_accumulate, dim3(grid), dim3(256), 0, st, acc, add, n, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_observe(const void* psi, int M, int site, double* partials, int nblk,
                           hipStream_t st) {
     hipLaunchKernelGGL(k_observe<T>, dim3(nblk), dim3(256), 0, st,
@@ -1385,6 +1435,8 @@ template hipError_t launch_init<float>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_init<double>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_init_product<float>(void*, int, int, uint64_t, hipStream_t);
 template hipError_t launch_init_product<double>(void*, int, int, uint64_t, hipStream_t);
+template hipError_t launch_init_members<float>(void*, int, int, int, uint64_t, uint64_t, hipStream_t);
+template hipError_t launch_init_members<double>(void*, int, int, int, uint64_t, uint64_t, hipStream_t);
 template hipError_t launch_observe<float>(const void*, int, int, double*, int, hipStream_t);
 template hipError_t launch_observe<double>(const void*, int, int, double*, int, hipStream_t);
 template hipError_t launch_factor<float>(void*, int, int, int, double, double, double, double, int,

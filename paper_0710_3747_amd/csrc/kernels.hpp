@@ -57,6 +57,14 @@ template <typename T>
 hipError_t launch_init(void* psi, int M, int n, uint64_t seed, hipStream_t st);
 template <typename T>
 hipError_t launch_init_product(void* psi, int M, int n, uint64_t seed, hipStream_t st);
+// Ensemble members first .. first + count - 1 stacked as one state of
+// M + cbits sites (member index on the top cbits bits, zeros beyond count).
+template <typename T>
+hipError_t launch_init_members(void* psi, int M, int cbits, int polarized, uint64_t first,
+                               uint64_t count, hipStream_t st);
+// acc[i] = (acc[i] + add[i]) * scale for i < n (add may be null).
+hipError_t launch_accumulate(double* acc, const double* add, int64_t n, double scale,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_observe(const void* psi, int M, int site, double* partials, int nblk,
                           hipStream_t st);

@@ -233,6 +233,41 @@ def test_batch_rejects_bad_init_and_basis_index():
     assert rc == spq.SPIN_EINVAL and "init" in spq.spin_last_error()
 
 
+ENSEMBLE_BAD = [
+    # (changes to the valid call, fragment of the message)
+    ({"prec": 9}, "prec"),
+    ({"M": 0}, "M = 0"),
+    ({"polarized": 4}, "polarized_site"),
+    ({"observed": -1}, "observed_site"),
+    ({"n_members": 0}, "n_members"),
+    ({"first": 1, "n_members": 8}, "member range"),
+    ({"first": -1}, "member range"),
+    ({"work_amps": 15}, "fewer than 2^M"),
+    ({"work": 0}, "psi is NULL"),
+    ({"work": 24}, "aligned"),
+    ({"P": None}, "P_dev"),
+    ({"n_steps": -1}, "n_steps"),
+    ({"dt": float("nan")}, "dt"),
+    ({"J": [(0, 4, 0.0, 1.0)]}, "site out of range"),
+]
+
+
+@pytest.mark.parametrize("change,frag", ENSEMBLE_BAD, ids=[f for _, f in ENSEMBLE_BAD])
+def test_ensemble_argument_checks(change, frag):
+    """spin_ensemble_evolve finds argument errors on the host before any
+    device work (fake device pointers are never dereferenced)."""
+    lib = spq.load_library()
+    a = {"prec": spq.SPIN_C64, "M": 4, "J": [(0, 1, 0.0, 1.0), (1, 2, 0.0, 1.0)], "dt": 0.1,
+         "n_steps": 3, "polarized": 0, "observed": 0, "first": 0, "n_members": 8, "work": 16,
+         "work_amps": 64, "P": 32}
+    a.update(change)
+    arr, K = spq._couplings(a["J"])
+    rc = lib.spin_ensemble_evolve(a["prec"], a["M"], arr, K, a["dt"], a["n_steps"], a["polarized"],
+                                  a["observed"], a["first"], a["n_members"], a["work"], a["work_amps"],
+                                  a["P"], None, None, None)
+    assert rc == spq.SPIN_EINVAL and frag in spq.spin_last_error()
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_random_graphs_plan_and_encode(seed):
     """Random coupling graphs, sizes, shapes and step counts: the host-only
