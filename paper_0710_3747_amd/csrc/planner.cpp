@@ -162,8 +162,38 @@ struct Sched {
         return first_pending >= ops.size();
     }
 
+    // Seed of the tile search grown breadth-first over the coupling graph
+    // of the pending factors, from the sites of the earliest pending one:
+    // a connected cluster, which the sequence-order seed misses when the
+    // list runs along one part of the graph first (a ladder's legs).
+    Mask cluster_seed(Mask forced) const {
+        Mask T = forced;
+        size_t n0 = first_pending;
+        while (n0 < ops.size() && (done[n0] || ops[n0].kind == 1)) ++n0;
+        if (n0 == ops.size()) return T;
+        std::vector<int> queue{ops[n0].i, ops[n0].j};
+        Mask seen = bit(ops[n0].i) | bit(ops[n0].j);
+        for (size_t q = 0; q < queue.size() && popc(T) < k; ++q) {
+            const int s = queue[q];
+            if (popc(T | bit(s)) > k) break;
+            T |= bit(s);
+            for (int n : site_ops[s]) {
+                const Op& op = ops[n];
+                if (done[n] || op.kind == 1 || op.step > limit) continue;
+                const int o = op.i == s ? op.j : op.i;
+                if (!(seen & bit(o))) {
+                    seen |= bit(o);
+                    queue.push_back(o);
+                }
+            }
+        }
+        return T;
+    }
+
     Mask choose_tile(Mask forced) {
-        // Seed: sites of the earliest pending ops, in sequence order.
+        // Seeds: sites of the earliest pending ops in sequence order, and a
+        // connected cluster around the earliest one; the local search runs
+        // from each and the better result is kept.
         Mask T = forced;
         for (size_t n = first_pending; n < ops.size() && popc(T) < k; ++n) {
             if (done[n] || ops[n].kind == 1) continue;
@@ -172,8 +202,21 @@ struct Sched {
             if (n - first_pending > 4096) break;
         }
         for (int s = 0; s < M && popc(T) < k; ++s) T |= bit(s);
+        double best = 0;
+        T = improve_tile(T, forced, &best);
+        Mask C = cluster_seed(forced);
+        for (int s = 0; s < M && popc(C) < k; ++s) C |= bit(s);
+        if (C != T) {
+            double v = 0;
+            C = improve_tile(C, forced, &v);
+            if (v > best + 1e-9) T = C;
+        }
+        return T;
+    }
+
+    // First-improvement local search over single-site swaps from T.
+    Mask improve_tile(Mask T, Mask forced, double* score) const {
         double best = closure(T, nullptr);
-        // First-improvement local search over single-site swaps.
         for (int round = 0; round < 64; ++round) {
             bool improved = false;
             for (int o2 = 0; o2 < M && !improved; ++o2) {
@@ -194,6 +237,7 @@ struct Sched {
             }
             if (!improved) break;
         }
+        *score = best;
         return T;
     }
 
@@ -778,6 +822,63 @@ HostPass schedule_one(Sched& sc, Relabel& rl, const std::vector<Op>& ops, int M,
     return hp;
 }
 
+// Sites away from their own address bit.
+Mask displaced(const Relabel& rl) {
+    Mask d = 0;
+    for (int s = 0; s < rl.M; ++s)
+        if (rl.pi[s] != s) d |= bit(s);
+    return d;
+}
+
+// The last pass of a run, when one pass can be it: a tile holding the
+// low-bit sites and every site away from its own bit whose closure is every
+// remaining op, stored with every site on its own bit.  A displaced site's
+// current bit is the own bit of another displaced site, so such a tile's
+// bits are exactly its sites' own bits and the store stays inside the
+// tile's addresses.  This saves the permutation-only pass that would
+// otherwise restore the layout.  Returns false, changing nothing, when no
+// such tile is found.
+bool try_finish(Sched& sc, Relabel& rl, const std::vector<Op>& ops, int M, HostPass* out) {
+    constexpr size_t kFinishOps = 256;   // only near the end of a run
+    if (sc.all_done()) return false;
+    size_t remaining = 0;
+    for (size_t n = sc.first_pending; n < ops.size() && remaining <= kFinishOps; ++n)
+        remaining += !sc.done[n];
+    if (remaining > kFinishOps) return false;
+    const Mask D = displaced(rl);
+    const Mask forced = rl.low_sites() | D;
+    if (popc(forced) > sc.k) return false;
+    const int64_t lim = sc.limit;
+    sc.limit = INT64_MAX;
+    const Mask T = sc.choose_tile(forced);
+    std::vector<int> applied;
+    sc.closure(T, &applied);
+    sc.limit = lim;
+    if (applied.size() != remaining) return false;
+    for (int n : applied) sc.mark_done(n);
+    HostPass hp = make_pass(ops, applied, T, M);
+    rl.keep(hp, T);
+    hp.bit_out = hp.sites;           // every site on its own bit
+    hp.writes = hp.writes || D != 0;
+    for (int s = 0; s < M; ++s) rl.pi[s] = s;
+    *out = std::move(hp);
+    return true;
+}
+
+// Schedules the remaining ops of `sc` and leaves the canonical layout.
+void schedule_to_end(Sched& sc, Relabel& rl, const std::vector<Op>& ops, int M, const PassParams& pp,
+                     int k, std::vector<HostPass>& out) {
+    while (!sc.all_done()) {
+        HostPass fin;
+        if (try_finish(sc, rl, ops, M, &fin)) {
+            out.push_back(std::move(fin));
+            break;
+        }
+        out.push_back(schedule_one(sc, rl, ops, M, pp));
+    }
+    for (HostPass& hp : rl.restore(k)) out.push_back(std::move(hp));
+}
+
 // Templates [t0, t0 + n) launched in order with observable labels shifted
 // by `offset`.
 void add_launches(StreamPlan& plan, int t0, int n, int64_t offset) {
@@ -806,8 +907,7 @@ std::vector<HostPass> plan_block(int M, const std::vector<Coupling>& J, double d
     sc.rotate = pp.rotate;
     Relabel rl(M, c);
     std::vector<HostPass> out;
-    while (!sc.all_done()) out.push_back(schedule_one(sc, rl, ops, M, pp));
-    for (HostPass& hp : rl.restore(k)) out.push_back(std::move(hp));
+    schedule_to_end(sc, rl, ops, M, pp, k, out);
     return out;
 }
 
@@ -944,8 +1044,7 @@ StreamPlan plan_stream_periodic(int M, const std::vector<Coupling>& J, double dt
         if (d1) tc.mark_done(int(n));
     }
     std::vector<HostPass> tail;
-    while (!tc.all_done()) tail.push_back(schedule_one(tc, tl, tops, M, pp));
-    for (HostPass& hp : tl.restore(k)) tail.push_back(std::move(hp));
+    schedule_to_end(tc, tl, tops, M, pp, k, tail);
     const int nt = int(tail.size());
     add_launches(plan, add_templates(plan, std::move(tail)), nt, 0);
     finish_stages(plan, pp);
