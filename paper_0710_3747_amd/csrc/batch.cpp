@@ -159,6 +159,7 @@ struct BatchCache {
          *d_stages = nullptr, *d_ops = nullptr, *d_launch = nullptr, *d_part = nullptr,
          *d_ctr = nullptr, *d_err = nullptr;
     int nslots = 0, ncounters = 0;
+    bool half = false;
     hipStream_t side = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -235,9 +236,10 @@ static std::vector<double> batch_key(const spin_problem* probs, int n,
 template <typename T>
 static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
                        const std::vector<std::vector<Coupling>>& Js, double dt, int64_t n_steps,
-                       int init, int nslots, BatchCache* bc) {
+                       int init, int nslots, bool half, BatchCache* bc) {
     const bool f32 = sizeof(T) == 4;
-    const int K = batch_tile_bits(f32), R = f32 ? 5 : 4, NT = 512, V = f32 ? 2 : 1;
+    const int K = batch_tile_bits(f32), R = batch_shape(f32, half).r;
+    const int KL = half ? K - 1 : K;    // largest problem held in LDS
     DevTables<T> tb;
     std::vector<BatchProblem> bp;
     std::vector<int2> launches;
@@ -262,7 +264,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
         if (hit != shared.end()) {
             b = hit->second.first;
             fops = hit->second.second;
-            if (b.gsize > 1 || b.M > K) {   // gang: own partial sums and counter
+            if (b.gsize > 1 || b.M > KL) {   // gang: own partial sums and counter
                 b.part0 = part;
                 part += int64_t(kBatchRing) * b.gsize * 2;
                 b.counter = ncounter++;
@@ -280,7 +282,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             bp.push_back(b);
             continue;
         }
-        if (pr.M <= K) {
+        if (pr.M <= KL) {
             ResidentPlan rp = plan_resident(pr.M, Js[p], dt, pr.observed_site, true, R);
             const int nthreads = 1 << (pr.M - R);
             b.gsize = 1;
@@ -301,6 +303,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
             // the library's default launch shape; a gang plans one scheduling
             // variant (plan_stream), not the single path's variant search
             pp.c = 4;
+            pp.half = half;
             StreamPlan sp = plan_stream(pr.M, Js[p], dt, n_steps, pr.observed_site, true, pp);
             b.pass0 = int(tb.passes.size());
             for (const HostPass& hp : sp.passes) encode_pass<T>(hp, pr.M, pr.observed_site, tb);
@@ -381,6 +384,7 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
     if ((rc = up(nullptr, std::max(ncounter, 1) * sizeof(int), &bc->d_ctr))) return rc;
     if ((rc = up(nullptr, sizeof(int), &bc->d_err))) return rc;
     bc->nslots = nslots;
+    bc->half = half;
     bc->ncounters = std::max(ncounter, 1);
     return SPIN_OK;
 }
@@ -388,12 +392,12 @@ static int batch_build(const spin_problem* probs, const std::vector<int>& sel,
 template <typename T>
 static int batch_persistent(const spin_problem* probs, const std::vector<int>& sel,
                             const std::vector<std::vector<Coupling>>& Js, int prec, double dt,
-                            int64_t n_steps, int init, bool use_graph, hipStream_t st) {
+                            int64_t n_steps, int init, bool use_graph, bool half, hipStream_t st) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(SPIN_EHIP, "hipGetDevice failed");
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(SPIN_EHIP, "device query failed");
-    const int nslots = prop.multiProcessorCount;   // one 512-lane, 128 KiB-LDS workgroup per CU
+    const int nslots = prop.multiProcessorCount * (half ? 2 : 1);
 
     // key over the selected problems only
     std::vector<spin_problem> ps;
@@ -404,6 +408,7 @@ static int batch_persistent(const spin_problem* probs, const std::vector<int>& s
     }
     std::vector<double> key = batch_key(ps.data(), int(ps.size()), js, prec, dt, n_steps, init, dev);
     key.push_back(use_graph ? 1 : 0);
+    key.push_back(half ? 1 : 0);
     std::shared_ptr<BatchCache> bc;
     {
         std::lock_guard<std::mutex> lk(g_bmu);
@@ -414,7 +419,7 @@ static int batch_persistent(const spin_problem* probs, const std::vector<int>& s
         bc = std::make_shared<BatchCache>();
         int rc;
         try {
-            rc = batch_build<T>(probs, sel, Js, dt, n_steps, init, nslots, bc.get());
+            rc = batch_build<T>(probs, sel, Js, dt, n_steps, init, nslots, half, bc.get());
         } catch (const std::exception& e) {
             return fail(SPIN_EUNSUPPORTED, std::string("batch planning failed: ") + e.what());
         }
@@ -425,7 +430,7 @@ static int batch_persistent(const spin_problem* probs, const std::vector<int>& s
     int* status = nullptr;
     if (int rc = status_word(dev, &status)) return rc;
     auto enqueue = [&](hipStream_t s) {
-        return launch_batch<T>(bc->nslots, static_cast<const BatchProblem*>(bc->d_probs),
+        return launch_batch<T>(bc->nslots, bc->half, static_cast<const BatchProblem*>(bc->d_probs),
                                static_cast<const BatchJob*>(bc->d_jobs),
                                static_cast<const int*>(bc->d_jstart),
                                static_cast<const DevPass*>(bc->d_passes),
@@ -506,9 +511,16 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
         (void)cap;
         if (n == 0) return SPIN_OK;
         hipStream_t st = static_cast<hipStream_t>(stream);
+        // Two workgroups per CU with half-tile gangs when both fit (every
+        // slot of the persistent launch must be resident at once), else one
+        // with whole tiles.
+        const bool f32 = prec == SPIN_C64;
+        const bool half = batch_blocks_per_cu(f32, true) >= 2;
+        if (!half && batch_blocks_per_cu(f32, false) < 1)
+            return fail(SPIN_EUNSUPPORTED, "batch kernel does not fit a CU");
         // states smaller than a lane's registers: the grouped one-workgroup
         // launches; everything else: the persistent launch
-        const int rmin = prec == SPIN_C64 ? 5 : 4;
+        const int rmin = batch_shape(f32, half).r;
         std::vector<int> small, big;
         for (int p = 0; p < n; ++p) (probs[p].M < rmin ? small : big).push_back(p);
         int rc = SPIN_OK;
@@ -525,8 +537,8 @@ extern "C" int spin_trotter_evolve_batch(const spin_problem* probs, int32_t n,
         }
         if (!big.empty()) {
             const bool graph = true;
-            rc = prec == SPIN_C64 ? batch_persistent<float>(probs, big, Js, prec, dt, n_steps, init, graph, st)
-                                  : batch_persistent<double>(probs, big, Js, prec, dt, n_steps, init, graph, st);
+            rc = f32 ? batch_persistent<float>(probs, big, Js, prec, dt, n_steps, init, graph, half, st)
+                     : batch_persistent<double>(probs, big, Js, prec, dt, n_steps, init, graph, half, st);
         }
         if (rc == SPIN_OK) fail(SPIN_OK, "");
         return rc;

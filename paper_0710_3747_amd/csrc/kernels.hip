@@ -1106,8 +1106,10 @@ __device__ __forceinline__ bool gang_barrier(int* counter, int target, int* err)
     return ok_s != 0;
 }
 
-template <typename T, int R, int NT>
-__global__ __launch_bounds__(NT) void k_batch(const BatchProblem* __restrict__ probs,
+// HALF: gangs run half-tile passes and two workgroups share a CU, so
+// problems held in LDS are limited to half a tile.
+template <typename T, int R, int NT, bool HALF>
+__global__ __launch_bounds__(NT, HALF ? 2 * NT / 256 : 1) void k_batch(const BatchProblem* __restrict__ probs,
                                               const BatchJob* __restrict__ jobs,
                                               const int* __restrict__ job_start,
                                               const DevPass* __restrict__ passes,
@@ -1119,14 +1121,18 @@ __global__ __launch_bounds__(NT) void k_batch(const BatchProblem* __restrict__ p
                                               int64_t n_steps) {
     using C = typename CT<T>::c;
     constexpr int K = R + __builtin_ctz(NT);
-    __shared__ C lds[1 << K];
-    __shared__ double red[2 * (NT / 64)];
+    constexpr int KL = HALF ? K - 1 : K;    // largest problem held in LDS
+    constexpr int NW = NT / 64;
+    __shared__ C lds[1 << KL];
+    __shared__ double red[2 * NW];
+    __shared__ double wacc[HALF ? NW : 1][2 * kMaxMeas];
     const int tid = threadIdx.x;
+    const int wave = tid / 64;
     for (int jb = job_start[blockIdx.x]; jb < job_start[blockIdx.x + 1]; ++jb) {
         const BatchJob job = jobs[jb];
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
         const BatchProblem& B = probs[job.problem];
-        if (B.gsize == 1 && B.M <= K) {
+        if (B.gsize == 1 && B.M <= KL) {
             ResidentJob J{};
             J.psi = B.psi;
             J.P = B.P;
@@ -1168,20 +1174,49 @@ __global__ __launch_bounds__(NT) void k_batch(const BatchProblem* __restrict__ p
             double accP[kMaxMeas], accN[kMaxMeas];
 #pragma unroll
             for (int m = 0; m < kMaxMeas; ++m) accP[m] = accN[m] = 0.0;
-            if (P.writes)
-                pass_tiles<T, R, NT, true>(psi, P, stages, ops, rank, G, tpm,
-                                           reinterpret_cast<char*>(lds), accP, accN);
-            else
-                pass_tiles<T, R, NT, false>(psi, P, stages, ops, rank, G, tpm,
-                                            reinterpret_cast<char*>(lds), accP, accN);
-            for (int m = 0; m < P.nmeas; ++m) {
-                double p, n;
-                slot_sum<NT>(accP, accN, m, red, p, n);
-                if (tid == 0) {
+            if constexpr (HALF) {
+                // per-wave observable rows (as k_pass), summed over the
+                // waves in a fixed order; the previous pass's reads of the
+                // rows finished before the gang barrier
+                if ((tid & 63) == 63)
+                    for (int m = 0; m < 2 * kMaxMeas; ++m) wacc[wave][m] = 0.0;
+                if (P.writes)
+                    pass_tiles<T, R, NT, true, 0, false, true>(psi, P, stages, ops, rank, G, tpm,
+                                                               reinterpret_cast<char*>(lds), accP, accN,
+                                                               nullptr, wacc[wave]);
+                else
+                    pass_tiles<T, R, NT, false, 0, false, true>(psi, P, stages, ops, rank, G, tpm,
+                                                                reinterpret_cast<char*>(lds), accP, accN,
+                                                                nullptr, wacc[wave]);
+                __syncthreads();
+                if (tid < P.nmeas) {
+                    const int m = tid;
+                    double p = 0.0, n = 0.0;
+                    for (int w = 0; w < NW; ++w) {
+                        p += wacc[w][2 * m];
+                        n += wacc[w][2 * m + 1];
+                    }
                     const int64_t s = int64_t(la.y) + P.meas_step[m];
                     double* dst = partials + B.part0 + ((s % kBatchRing) * G + rank) * 2;
                     dst[0] = p;
                     dst[1] = n;
+                }
+            } else {
+                if (P.writes)
+                    pass_tiles<T, R, NT, true>(psi, P, stages, ops, rank, G, tpm,
+                                               reinterpret_cast<char*>(lds), accP, accN);
+                else
+                    pass_tiles<T, R, NT, false>(psi, P, stages, ops, rank, G, tpm,
+                                                reinterpret_cast<char*>(lds), accP, accN);
+                for (int m = 0; m < P.nmeas; ++m) {
+                    double p, n;
+                    slot_sum<NT>(accP, accN, m, red, p, n);
+                    if (tid == 0) {
+                        const int64_t s = int64_t(la.y) + P.meas_step[m];
+                        double* dst = partials + B.part0 + ((s % kBatchRing) * G + rank) * 2;
+                        dst[0] = p;
+                        dst[1] = n;
+                    }
                 }
             }
             ok = gang_barrier(ctr, ++epoch * int(G), err);
@@ -1402,8 +1437,28 @@ hipError_t launch_resident(int r, int nt, const ResidentJob& job0, const Residen
 
 int batch_tile_bits(bool f32) { return f32 ? 14 : 13; }
 
+// Launch shapes of the batch kernel: whole tiles 2^R x 512 lanes (one
+// workgroup per CU); half tiles 2^(R+1) x 256 lanes (two per CU), whose
+// larger register stages take fewer LDS exchanges on dense coupling graphs.
+BatchShape batch_shape(bool f32, bool half) {
+    if (half) return BatchShape{true, f32 ? 6 : 5, 256};
+    return BatchShape{false, f32 ? 5 : 4, 512};
+}
+
+int batch_blocks_per_cu(bool f32, bool half) {
+    int n = 0;
+    hipError_t e;
+    if (f32)
+        e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float, 6, 256, true>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float, 5, 512, false>, 512, 0);
+    else
+        e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double, 5, 256, true>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double, 4, 512, false>, 512, 0);
+    return e == hipSuccess ? n : 0;
+}
+
 template <typename T>
-hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* jobs,
+hipError_t launch_batch(int nslots, bool half, const BatchProblem* probs, const BatchJob* jobs,
                         const int* job_start, const DevPass* passes, const DevStage* stages,
                         const DevOp<T>* ops, const int2* launches, double* partials, int* counters,
                         int ncounters, int* err, int* status, int64_t n_steps, hipStream_t st) {
@@ -1411,23 +1466,24 @@ hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* j
     // memset node, so the pair can sit in a captured graph)
     hipLaunchKernelGGL(k_fill_int, dim3(64), dim3(256), 0, st, counters, ncounters, 0);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, err, 1, 0);
-    if constexpr (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_batch<T, 5, 512>), dim3(nslots), dim3(512), 0, st, probs, jobs,
-                           job_start, passes, stages, ops, launches, partials, counters, err,
+    constexpr bool F = sizeof(T) == 4;
+    if (half)
+        hipLaunchKernelGGL((k_batch<T, F ? 6 : 5, 256, true>), dim3(nslots), dim3(256), 0, st, probs,
+                           jobs, job_start, passes, stages, ops, launches, partials, counters, err,
                            n_steps);
     else
-        hipLaunchKernelGGL((k_batch<T, 4, 512>), dim3(nslots), dim3(512), 0, st, probs, jobs,
-                           job_start, passes, stages, ops, launches, partials, counters, err,
+        hipLaunchKernelGGL((k_batch<T, F ? 5 : 4, 512, false>), dim3(nslots), dim3(512), 0, st, probs,
+                           jobs, job_start, passes, stages, ops, launches, partials, counters, err,
                            n_steps);
     hipLaunchKernelGGL(k_status_or, dim3(1), dim3(64), 0, st, err, status);
     return hipGetLastError();
 }
 
-template hipError_t launch_batch<float>(int, const BatchProblem*, const BatchJob*, const int*,
+template hipError_t launch_batch<float>(int, bool, const BatchProblem*, const BatchJob*, const int*,
                                         const DevPass*, const DevStage*, const DevOp<float>*,
                                         const int2*, double*, int*, int, int*, int*, int64_t,
                                         hipStream_t);
-template hipError_t launch_batch<double>(int, const BatchProblem*, const BatchJob*, const int*,
+template hipError_t launch_batch<double>(int, bool, const BatchProblem*, const BatchJob*, const int*,
                                          const DevPass*, const DevStage*, const DevOp<double>*,
                                          const int2*, double*, int*, int, int*, int*, int64_t,
                                          hipStream_t);

@@ -81,13 +81,22 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
                        int64_t tiles_per_wg, int nwg, double* partials, int64_t step_offset,
                        int ch, hipStream_t st);
 // Persistent batch launch over `nslots` workgroups (all resident at once);
-// a gang-barrier time-out sets `err` and is or-ed into `*status`.
+// a gang-barrier time-out sets `err` and is or-ed into `*status`.  half:
+// gangs run half-tile passes (two workgroups per CU) and problems held in
+// LDS have at most tile bits - 1 sites.  Launch shape: batch_shape.
 template <typename T>
-hipError_t launch_batch(int nslots, const BatchProblem* probs, const BatchJob* jobs,
+hipError_t launch_batch(int nslots, bool half, const BatchProblem* probs, const BatchJob* jobs,
                         const int* job_start, const DevPass* passes, const DevStage* stages,
                         const DevOp<T>* ops, const int2* launches, double* partials, int* counters,
                         int ncounters, int* err, int* status, int64_t n_steps, hipStream_t st);
 int batch_tile_bits(bool f32);
+struct BatchShape {
+    bool half;
+    int r, nt;    // register bits, lanes; tile bits r + log2(nt) = batch_tile_bits
+};
+BatchShape batch_shape(bool f32, bool half);
+// Workgroups of the batch kernel that fit one CU at once (0 on error).
+int batch_blocks_per_cu(bool f32, bool half);
 
 template <typename T>
 hipError_t launch_resident(int r, int nt, const ResidentJob& job0, const ResidentJob* jobs,

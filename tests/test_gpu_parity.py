@@ -260,12 +260,13 @@ def test_batch_matches_single_runs(prec):
     assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for p in probs:
-        # gangs plan whole-tile exchanges (the persistent launch keeps one
-        # workgroup per CU); the single path is asked for the same
-        P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"],
-                                  opts={"exchange": 1})
-        assert np.array_equal(p["P"].cpu().numpy(), P)
-        assert np.array_equal(p["psi"].cpu().numpy().astype(np.complex128), psi)
+        # problems held in LDS use the batch's register stages and the
+        # largest ones run as a one-workgroup gang of tiled passes, so the
+        # rotations' shears may run in the other order of a pair: equal to
+        # rounding
+        P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
+        assert np.abs(p["P"].cpu().numpy() - P).max() < TOL_P[prec]
+        assert_state_close(p["psi"].cpu().numpy().astype(np.complex128), psi, prec)
     # and one against the oracle
     p = probs[0]
     Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
@@ -275,9 +276,10 @@ def test_batch_matches_single_runs(prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_batch_gangs_match_single_runs(prec):
     """Problems larger than one workgroup run as gangs of workgroups inside
-    the persistent launch; states must equal the single-problem path's with
-    whole-tile exchanges bit for bit (same plan, same arithmetic) and P agree
-    to FP64 rounding."""
+    the persistent launch.  Where the single-problem path runs the same plan
+    (tiled, at the gangs' launch shape) states must agree bit for bit and P
+    to FP64 rounding; the others (held in LDS, or one tile run as a gang of
+    one) agree to the parity tolerances."""
     import torch
     Ms = [15, 14, 16, 17, 18, 6, 15]
     steps, dt = 30, 0.02
@@ -293,11 +295,18 @@ def test_batch_gangs_match_single_runs(prec):
     assert spq.spin_batch_status() == 0, spq.spin_last_error()
     torch.cuda.synchronize()
     for p in probs:
-        # gangs plan whole-tile exchanges; the single path is asked for the same
+        # the gangs' launch shape: 64 amplitudes per lane (32 in complex128)
+        # with half-tile exchanges
+        shape = (14, 6, 4) if prec == C64 else (13, 5, 4)
         P, N, psi, _ = gpu_evolve(prec, p["M"], p["couplings"], dt, steps, 0, seed=p["seed"],
-                                  opts={"exchange": 1})
-        assert np.abs(p["P"].cpu().numpy() - P).max() < 1e-13
-        assert np.array_equal(p["psi"].cpu().numpy().astype(np.complex128), psi)
+                                  opts=dict(zip(("tile_bits", "reg_bits", "coalesce_bits"), shape)))
+        got = p["psi"].cpu().numpy().astype(np.complex128)
+        if p["M"] > shape[0]:
+            assert np.abs(p["P"].cpu().numpy() - P).max() < 1e-13
+            assert np.array_equal(got, psi)
+        else:
+            assert np.abs(p["P"].cpu().numpy() - P).max() < TOL_P[prec]
+            assert_state_close(got, psi, prec)
     p = probs[0]
     Pw, _, psiw = oracle_run(p["M"], p["couplings"], dt, steps, 0, seed=p["seed"])
     assert np.abs(p["P"].cpu().numpy() - Pw).max() < TOL_P[prec]
