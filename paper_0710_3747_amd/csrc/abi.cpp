@@ -186,7 +186,9 @@ Shape choose_shape(int prec, int M, const spin_options* opt) {
     s.c = 4;
     if (opt && opt->tile_bits > 0) {
         k = opt->tile_bits;
-        s.r = f32 ? (k <= 12 ? 4 : 5) : (ex != 1 && k == 13 ? 5 : 4);
+        // complex128: 32 amplitudes per lane with half tiles of 2^13 (two
+        // 256-lane workgroups per CU) or 2^14 (one 512-lane workgroup)
+        s.r = f32 ? (k <= 12 ? 4 : 5) : (ex != 1 && (k == 13 || k == 14) ? 5 : 4);
     }
     if (opt && opt->reg_bits > 0) s.r = opt->reg_bits;
     if (opt && opt->coalesce_bits > 0) s.c = opt->coalesce_bits;

@@ -128,14 +128,15 @@ spin_options to_options(const Tuned& t) {
 // matrix engine is not among them: a dense stage matrix costs about 20x the
 // flops of the butterflies it replaces and it removes no LDS exchange, so it
 // never wins on these workloads (it stays selectable through spin_options).
-// Exchange 2 = half tiles (two workgroups per CU), 1 = whole tiles.
+// Exchange 2 = half tiles (two workgroups per CU; one for complex128 tiles
+// of 2^14), 1 = whole tiles.
 std::vector<Tuned> candidates(int32_t prec) {
     if (prec == SPIN_C64)
         return {{14, 5, 4, 0, 2, 0}, {14, 5, 5, 0, 2, 0}, {14, 5, 6, 0, 2, 0}, {14, 6, 4, 0, 2, 0},
                 {14, 5, 4, 0, 1, 0}, {14, 5, 6, 0, 1, 0}, {14, 4, 4, 0, 1, 0}, {13, 5, 5, 0, 1, 0},
                 {13, 4, 4, 0, 1, 0}};
-    return {{13, 4, 4, 0, 2, 0}, {13, 5, 4, 0, 2, 0}, {13, 4, 4, 0, 1, 0}, {13, 5, 4, 0, 1, 0},
-            {12, 4, 4, 0, 1, 0}};
+    return {{13, 4, 4, 0, 2, 0}, {13, 5, 4, 0, 2, 0}, {14, 5, 4, 0, 2, 0}, {13, 4, 4, 0, 1, 0},
+            {13, 5, 4, 0, 1, 0}, {12, 4, 4, 0, 1, 0}};
 }
 
 struct DeviceBuffers {

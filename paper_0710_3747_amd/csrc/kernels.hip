@@ -875,8 +875,16 @@ __device__ __forceinline__ void slot_sum(const double (&accP)[kMaxMeas],
 // every site, then N).
 // HALF: half-tile exchanges, LDS for half a tile, no register prefetch, and
 // registers capped so that two workgroups share a CU.
+// Waves per SIMD a half-tile pass kernel is built for: two workgroups per
+// CU when their half-tile LDS buffers fit the CU's 160 KiB together (with
+// room for the small arrays), else one (complex128 tiles of 2^14).
+template <typename T, int R, int NT>
+__host__ __device__ constexpr int half_waves_per_eu() {
+    return ((sizeof(typename CT<T>::c) << (R + __builtin_ctz(NT) - 1)) <= 72 * 1024 ? 2 : 1) * NT / 256;
+}
+
 template <typename T, int R, int NT, bool WRITES, int ENGINE, bool PROFILE, bool HALF>
-__global__ __launch_bounds__(NT, HALF ? 2 * NT / 256 : 1) void k_pass(typename CT<T>::c* __restrict__ psi,
+__global__ __launch_bounds__(NT, (HALF ? half_waves_per_eu<T, R, NT>() : 1)) void k_pass(typename CT<T>::c* __restrict__ psi,
                                              const DevPass* __restrict__ passes,
                                              const DevStage* __restrict__ stages,
                                              const DevOp<T>* __restrict__ ops, int pass_index,
@@ -1342,7 +1350,7 @@ static hipError_t pass_one(bool writes, void* psi, const DevPass* passes, const 
 
 bool pass_half_exists(bool f32, int r, int nt) {
     if (f32) return (r == 5 && nt == 512) || (r == 6 && nt == 256);
-    return (r == 4 && nt == 512) || (r == 5 && nt == 256);
+    return (r == 4 && nt == 512) || (r == 5 && nt == 256) || (r == 5 && nt == 512);
 }
 
 bool pass_shape_exists(bool f32, int r, int nt, int engine) {
@@ -1381,7 +1389,7 @@ hipError_t launch_pass(const PassShape& sh, void* psi, const DevPass* passes,
         if constexpr (sizeof(T) == 4) {
             SPIN_HALF(5, 512) SPIN_HALF(6, 256)
         } else {
-            SPIN_HALF(4, 512) SPIN_HALF(5, 256)
+            SPIN_HALF(4, 512) SPIN_HALF(5, 256) SPIN_HALF(5, 512)
         }
 #undef SPIN_HALF
         return hipErrorInvalidValue;

@@ -116,7 +116,7 @@ def ladder30():
 # between for the benchmark (tile bits, register bits, coalescing bits, and
 # exchange 1 = whole tiles where given)
 LADDER_SHAPES = [(C128, None), (C64, None), (C64, (14, 5, 5)), (C64, (14, 5, 6)), (C64, (14, 6, 4)),
-                 (C64, (14, 5, 4, 1)), (C64, (14, 4, 4, 1)), (C128, (13, 4, 4, 1))]
+                 (C64, (14, 5, 4, 1)), (C64, (14, 4, 4, 1)), (C128, (13, 4, 4, 1)), (C128, (14, 5, 4))]
 
 
 def _shape_id(p, s):

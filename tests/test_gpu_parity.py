@@ -151,6 +151,10 @@ TILED = [
     # 128-byte runs (complex64: 16 amplitudes), 512 and 1024 lanes
     ("ladder20-c4", 20, workloads.ladder(10), 0.05, 30, 0, 0, {"coalesce_bits": 4}),
     ("ladder20-r4-c4", 20, workloads.ladder(10), 0.05, 30, 0, 0, {"reg_bits": 4, "coalesce_bits": 4}),
+    # tiles of 2^14 amplitudes with half-tile exchanges (complex128: one
+    # 512-lane workgroup per CU, 32 amplitudes per lane)
+    ("ladder20-k14", 20, workloads.ladder(10), 0.05, 30, 0, 0, {"tile_bits": 14, "coalesce_bits": 4}),
+    ("star17-k14-zz", 17, workloads.star(17, 8, a_over_b=-2.0), 0.02, 6, 2, 5, {"tile_bits": 14}),
 ]
 
 
@@ -158,8 +162,8 @@ TILED = [
 @pytest.mark.parametrize("case", TILED, ids=[c[0] for c in TILED])
 def test_tiled_path_matches_oracle(prec, case):
     name, M, J, dt, steps, obs, pol, opts = case
-    if prec == C128 and opts.get("tile_bits", 0) > 13:
-        pytest.skip("complex128 tiles hold at most 2^13 amplitudes")
+    if prec == C128 and opts.get("tile_bits", 0) > 14:
+        pytest.skip("complex128 tiles hold at most 2^14 amplitudes")
     if prec == C64 and opts.get("reg_bits") == 4 and opts.get("tile_bits") not in (None, 12):
         pytest.skip("no such complex64 shape")
     note("tiled", name, prec)

@@ -337,6 +337,7 @@ EXCHANGE_CASES = [
     ("ladder2x15-c64-k14r4c4", 30, workloads.ladder(15), 1, 14, 4, 4, 100, 0),
     ("ladder2x15-c128-k13r4c4-half", 30, workloads.ladder(15), 2, 13, 4, 4, 100, 1),
     ("ladder2x15-c128-k13r5c4-half", 30, workloads.ladder(15), 2, 13, 5, 4, 100, 1),
+    ("ladder2x15-c128-k14r5c4-half", 30, workloads.ladder(15), 2, 14, 5, 4, 100, 1),
     ("star28-c64-k14r5c6-half", 28, workloads.star(28, 33), 1, 14, 5, 6, 12, 1),
     ("star28-blocks-c64-k14r6c4-half", 28, workloads.star_m28(), 1, 14, 6, 4, 12, 1),
     ("star20-c64-k14r5c4", 20, workloads.star(20, 2000), 1, 14, 5, 4, 60, 0),
