@@ -206,3 +206,23 @@ def test_ensemble_is_deterministic_and_chunking_invariant():
     c, _ = gpu_ensemble(C128, M, J, dt, steps, 0, 0, work_members=3 * 2 ** 12)
     assert np.array_equal(a, b)
     assert np.abs(a - c).max() < 1e-12
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=["c64", "c128"])
+def test_ensemble_tiny_closed_forms(prec):
+    """M = 1: the one member keeps P = 1.  M = 2 with one XY bond b: member
+    |up, up> keeps P = 1 and |up, down> has P = cos(b t), so the ensemble
+    P(t) = (1 + cos(b t)) / 2 (section "Spin systems with different coupling
+    networks", single pair); the Strang step is exact for one factor."""
+    note("ensemble tiny", prec)
+    P, N = gpu_ensemble(prec, 1, [], 0.1, 5, 0, 0)
+    assert np.abs(P - 1).max() < TOL_P[prec] and np.abs(N - 1).max() < TOL_P[prec]
+    b, dt, steps = 1.3, 0.07, 60
+    for pol, obs in ((0, 0), (1, 1)):
+        P, N = gpu_ensemble(prec, 2, [(0, 1, 0.0, b)], dt, steps, pol, obs, work_members=1)
+        t = dt * np.arange(steps + 1)
+        assert np.abs(P - 0.5 * (1 + np.cos(b * t))).max() < TOL_P[prec]
+    # observing the partner site: member |up, up> gives +1, member
+    # |up, down> gives -cos(b t), so P(t) = (1 - cos(b t)) / 2
+    P, N = gpu_ensemble(prec, 2, [(0, 1, 0.0, b)], dt, steps, 0, 1, work_members=2)
+    assert np.abs(P - 0.5 * (1 - np.cos(b * t))).max() < TOL_P[prec]
