@@ -7,13 +7,13 @@ against:
 * the oracle's Trotterised ensemble average (``ed.ensemble_P_trotter``,
   sector by sector) over every step at M = 8..12, and on a 3-step prefix of
   the whole 2 x 7 ladder (M = 14);
-* member ranges at M = 16 and 18 (2 x 8 and 2 x 9 XY ladders, 100 steps)
+* member ranges at M = 16, 18 and 20 (2 x 8, 2 x 9, 2 x 10 XY ladders, 100 steps)
   against the mean of the oracle's Trotter loop run on each member's basis
   state, with ragged member counts and evolutions of a few members;
 * the whole ensemble of an XY chain at M = 18 (2^17 members): the
   free-fermion closed form |g_00|^2 of the Trotterised single-particle
   propagator at every step;
-* the whole ensemble of the 2 x 8 and 2 x 9 ladders on the first two steps:
+* the whole ensemble of the 2 x 8, 2 x 9 and 2 x 10 ladders on the first two steps:
   after k Strang steps (list order: even leg bonds, odd leg bonds, rungs)
   site 0's Heisenberg operator reaches leg sites 0..2k+1 only, so the
   ensemble P of any 2 x L ladder with L >= 2k+2 equals that of the 2 x 6
@@ -129,6 +129,7 @@ RANGE_CASES = [
     (8, 0, 0, [(0, 5), (2 ** 14 - 3, 7), (2 ** 15 - 4, 4)], 2),
     (8, 3, 0, [(1000, 9)], 4),
     (9, 0, 0, [(0, 3), (2 ** 16 + 11, 5), (2 ** 17 - 6, 6)], 4),
+    (10, 7, 0, [(0, 2), (2 ** 19 - 5, 5)], 2),
 ]
 
 
@@ -136,7 +137,7 @@ RANGE_CASES = [
 @pytest.mark.parametrize("prec", PRECS, ids=["c64", "c128"])
 @pytest.mark.parametrize("case", RANGE_CASES, ids=lambda c: f"2x{c[0]}-p{c[1]}o{c[2]}")
 def test_member_ranges_match_member_runs(prec, case):
-    """Member ranges at M = 16 and 18 against the oracle loop on each
+    """Member ranges at M = 16, 18 and 20 against the oracle loop on each
     member's basis state, 100 steps."""
     L, pol, obs, ranges, wm = case
     M, J, dt, steps = 2 * L, workloads.ladder(L), 0.05, 100
@@ -166,10 +167,11 @@ def test_whole_ensemble_xy_chain_M18_free_fermions(prec):
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("prec", PRECS, ids=["c64", "c128"])
-@pytest.mark.parametrize("L", [8, 9])
+@pytest.mark.parametrize("L", [8, 9, 10])
 def test_whole_ladder_ensemble_two_steps_light_cone(prec, L):
-    """The whole ensemble of the 2 x L ladder (M = 16, 18) after 0..2 steps
-    equals the oracle's ensemble of the 2 x 6 ladder (light cone)."""
+    """The whole ensemble of the 2 x L ladder (M = 16, 18, 20; 2^19 members
+    at M = 20) after 0..2 steps equals the oracle's ensemble of the 2 x 6
+    ladder (light cone)."""
     M, steps = 2 * L, 2
     note("ensemble light cone", M, prec)
     P, N = gpu_ensemble(prec, M, workloads.ladder(L), 0.05, steps, 0, 0, work_members=2 ** 12)
