@@ -158,7 +158,7 @@ def star28():
     orc.release()
 
 
-STAR_SHAPES = [(C128, None), (C64, None), (C64, (14, 6, 4))]
+STAR_SHAPES = [(C128, None), (C64, None), (C64, (14, 6, 4)), (C128, (14, 5, 4))]
 STAR_IDS = [_shape_id(p, s) for p, s in STAR_SHAPES]
 
 
