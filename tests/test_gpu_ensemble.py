@@ -228,3 +228,23 @@ def test_ensemble_tiny_closed_forms(prec):
     # |up, down> gives -cos(b t), so P(t) = (1 - cos(b t)) / 2
     P, N = gpu_ensemble(prec, 2, [(0, 1, 0.0, b)], dt, steps, 0, 1, work_members=2)
     assert np.abs(P - 0.5 * (1 - np.cos(b * t))).max() < TOL_P[prec]
+
+
+ENSEMBLE_OPTS = [{"schedule": 1}, {"exchange": 1, "tile_bits": 13}, {"use_graph": 1},
+                 {"tile_bits": 12, "reg_bits": 4}]
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=["c64", "c128"])
+@pytest.mark.parametrize("opts", ENSEMBLE_OPTS, ids=lambda o: "-".join(f"{k}{v}" for k, v in o.items()))
+def test_ensemble_options_reach_the_evolutions(prec, opts):
+    """Launch options pass through to the stacked evolutions: the unfused
+    schedule, whole-tile exchanges, graph replay and small tiles all give the
+    oracle's ensemble (2 x 5 ladder with ZZ, polarised site 3, observed 6;
+    64 members per evolution, 8 evolutions)."""
+    name, M, steps, pol, obs = "ladder_2x5_zz", 10, 30, 3, 6
+    note("ensemble options", prec, opts)
+    P, N = gpu_ensemble(prec, M, SMALL_J[name], SMALL_DT[name], steps, pol, obs, work_members=64,
+                        opts=opts)
+    want = oracle_ensemble(name, M, steps, pol, obs)
+    assert np.abs(P - want).max() < TOL_P[prec], np.abs(P - want).max()
+    assert np.abs(N - 1).max() < TOL_P[prec]
