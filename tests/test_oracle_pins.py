@@ -399,3 +399,22 @@ def test_product_phases_are_the_counter_generator_outputs():
     psi = oracle.product_state(M, n, ph)
     x = 0b101001   # sites 0, 3, 5 down; up sites other than n: 1, 4
     assert abs(psi[x] - np.exp(-1j * (ph[1] + ph[4])) / np.sqrt(2.0 ** (M - 1))) < 1e-15
+
+
+def test_ladder_ensemble_light_cone():
+    """Light cone of the ladder's Strang step (list order: even leg bonds, odd
+    leg bonds, rungs): after k steps site 0's Heisenberg operator reaches leg
+    sites 0..2k+1 only, so the infinite-temperature ensemble P of Eq. (1) at
+    site 0 is the same for every 2 x L ladder with L >= 2k + 2 (a sufficient
+    condition).  Checked on the oracle's Trotterised ensemble average for
+    k <= 1 (L = 4, 5, 6); a ladder too short for any cone (2 x 2) already
+    differs after one step, so the quantity does see the far sites.  The GPU
+    tests of the brute-force ensemble at M = 16..20 rely on it for k <= 2."""
+    dt = 0.05
+    p4 = ed.ensemble_P_trotter(8, workloads.ladder(4), dt, 1, 0, 0)
+    p5 = ed.ensemble_P_trotter(10, workloads.ladder(5), dt, 1, 0, 0)
+    p6 = ed.ensemble_P_trotter(12, workloads.ladder(6), dt, 2, 0, 0)
+    assert np.abs(p4 - p5).max() < 1e-14 and np.abs(p4 - p6[:2]).max() < 1e-14
+    p2 = ed.ensemble_P_trotter(4, workloads.ladder(2), dt, 1, 0, 0)
+    assert np.abs(p2[1] - p4[1]) > 1e-8
+    assert p6[2] < 1 - 1e-3                        # the dynamics has started
