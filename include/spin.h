@@ -129,7 +129,9 @@ int spin_trotter_evolve(void *psi, int32_t prec, int32_t M, const spin_coupling 
 typedef struct {
     int32_t schedule;     /* 0 = fused tiles (default); 1 = one full pass per factor
                              (the plain, unfused schedule, kept as a cross-check) */
-    int32_t tile_bits;    /* k of the 2^k-amplitude tiles; 0 = autotuned / default */
+    int32_t tile_bits;    /* k of the 2^k-amplitude tiles; 0 = default (14 for
+                             complex64, 13 for complex128; complex128 also takes 14,
+                             with half tiles and one workgroup per CU) */
     int32_t reg_bits;     /* amplitudes per lane = 2^reg_bits; 0 = default */
     int32_t coalesce_bits;/* low address bits every tile keeps; 0 = default (4) */
     int32_t engine;       /* 0 = VALU butterflies (default); 1 = each register stage's
@@ -147,7 +149,8 @@ typedef struct {
                              1 = whole tiles (one workgroup per CU, the next tile
                              prefetched into registers); 2 = half tiles (one tile
                              position stays in registers in every stage, the tile moves
-                             through LDS in two halves, two workgroups share a CU) */
+                             through LDS in two halves, two workgroups share a CU, one
+                             for complex128 tiles of 2^14) */
     int32_t reserved[8];
 } spin_options;
 
