@@ -123,8 +123,11 @@ def summarize(res, w, steps, prec_bytes):
     avg_launch_s = sec / launches
     alg_per_launch = sweep * steps / launches
     achieved = alg_per_launch / avg_launch_s / 1e9
+    # every stage exchange writes and reads each amplitude once through LDS
+    lds_bytes = info["exchanges"] * 2 * state_bytes
     return dict(value=amp_updates / sec, ms_per_step=res["ms_total"] / steps,
                 passes_per_step=info["passes_per_step"], launches=launches,
+                lds_bytes_per_step=lds_bytes / steps, lds_TBs=lds_bytes / sec / 1e12,
                 avg_pass_ms=avg_launch_s * 1e3, achieved_gbs=achieved,
                 alg_bytes_per_launch=alg_per_launch, alg_bytes_per_step=sweep,
                 sweep_gbs_per_pass=sweep / avg_launch_s / 1e9,
@@ -192,10 +195,20 @@ def run_batch(spq, torch, prec=None, reps=2):
            "amplitude_updates": upd,
            "state_bytes": sum((8 if prec == spq.SPIN_C64 else 16) * 2 ** p["M"] for p in spec)}
     if prec == spq.SPIN_C64:
+        # LDS bytes of the stage exchanges, estimated from one problem of each
+        # size planned on the single path at the batch's launch shape
+        o = spq.Options(tile_bits=14, reg_bits=6, coalesce_bits=4)
+        lds, seen = 0.0, {}
+        for p in spec:
+            if p["M"] not in seen:
+                info = spq.spin_describe_plan(prec, p["M"], p["couplings"], dt, steps, 0, o)
+                seen[p["M"]] = info["exchanges"] * 2 * 8 * 2 ** p["M"]
+            lds += seen[p["M"]]
         out["roofline"] = {"bound": "alu", "achieved": flops / sec / 1e12,
                            "peak": VALU_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": flops / sec / 1e12 / VALU_F32_PEAK_TFLOPS, "traffic": None,
                            "flops_per_amplitude_update": FLOPS_PER_AMP_UPDATE,
+                           "lds_bytes_estimate": lds, "lds_TBs_estimate": lds / sec / 1e12,
                            "kernel": "k_batch"}
     return out, np.stack([p["P"].cpu().numpy() for p in probs])
 
@@ -521,6 +534,9 @@ def main():
                      "alg_bytes_per_launch": s["alg_bytes_per_launch"],
                      "alg_bytes_per_step": s["alg_bytes_per_step"],
                      "frac_per_pass": s["sweep_gbs_per_pass"] / HBM_PEAK_GBS,
+                     # LDS bytes of the stage exchanges (from the plan) and
+                     # their rate over the timed region
+                     "lds_bytes_per_step": s["lds_bytes_per_step"], "lds_TBs": s["lds_TBs"],
                      "kernel": "k_pass", "avg_launch_ms": s["avg_pass_ms"],
                      "launches": s["launches"],
                      # a state within the 256 MB Infinity Cache streams from

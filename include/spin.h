@@ -414,6 +414,10 @@ typedef struct {
     int64_t launches;       /* pass-kernel launches for the whole call */
     int64_t factor_ops;     /* two-spin factor applications after merging, whole call */
     double passes_per_step; /* launches / n_steps (path 2) */
+    int64_t exchanges;      /* stage exchanges through LDS over the whole call: each
+                               writes and reads every amplitude once (path 2: register
+                               stages after the first of each launch; path 1: every
+                               stage, the state lives in LDS) */
 } spin_plan_info;
 
 int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling *J, int32_t K, double dt,

@@ -80,7 +80,7 @@ class _PlanInfo(ctypes.Structure):
                 ("stages_total", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("exchange", ctypes.c_int32), ("reserved_", ctypes.c_int32),
                 ("launches", ctypes.c_int64), ("factor_ops", ctypes.c_int64),
-                ("passes_per_step", ctypes.c_double)]
+                ("passes_per_step", ctypes.c_double), ("exchanges", ctypes.c_int64)]
 
 
 def library_path() -> str:

@@ -888,6 +888,7 @@ extern "C" int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling* 
         info->reg_bits = hp.res_r;
         info->launches = 1;
         info->stages_total = int(hp.rp.prologue.stages.size() + hp.rp.step.stages.size());
+        info->exchanges = int64_t(hp.rp.prologue.stages.size()) + n_steps * int64_t(hp.rp.step.stages.size());
         int64_t f = 0;
         for (const Op& op : hp.rp.step.ops) f += op.kind == 0;
         info->factor_ops = f * n_steps;
@@ -906,8 +907,10 @@ extern "C" int spin_describe_plan(int32_t prec, int32_t M, const spin_coupling* 
         info->stages_total = int(st);
         info->launches = int64_t(hp.sp.launch_tmpl.size());
         int64_t f = 0;
-        for (int t : hp.sp.launch_tmpl)
+        for (int t : hp.sp.launch_tmpl) {
             for (const Op& op : hp.sp.passes[t].ops) f += op.kind == 0;
+            info->exchanges += int64_t(hp.sp.passes[t].stages.size()) - 1;
+        }
         info->factor_ops = f;
         info->passes_per_step = hp.sp.passes_per_step();
     }

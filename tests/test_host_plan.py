@@ -367,3 +367,18 @@ def test_exchange_check_reports_a_planted_cross_wave_exchange(tmp_path_factory):
     rc, out = _run_exchange_check(_exchange_check_binary(tmp_path_factory), 30, workloads.ladder(15), 1,
                                   14, 5, 4, 40, plant=1)
     assert rc == 1 and "moves amplitudes between waves" in out
+
+
+def test_describe_counts_stage_exchanges():
+    """spin_plan_info.exchanges: the state held by one workgroup does one LDS
+    round trip per stage (prologue once, the step's stages every step); a
+    tiled plan does one per register stage after the first of each launch."""
+    J = workloads.ladder(5)
+    d0 = spq.spin_describe_plan(spq.SPIN_C64, 10, J, 0.05, 0, 0)
+    d7 = spq.spin_describe_plan(spq.SPIN_C64, 10, J, 0.05, 7, 0)
+    assert d0["path"] == 1 and d0["exchanges"] > 0
+    assert (d7["exchanges"] - d0["exchanges"]) % 7 == 0 and d7["exchanges"] > d0["exchanges"]
+    t = spq.spin_describe_plan(spq.SPIN_C64, 18, workloads.ladder(9), 0.05, 40, 0)
+    assert t["path"] == 2
+    assert 0 < t["exchanges"] < t["launches"] * 64
+    assert t["exchanges"] >= t["stages_total"] - t["templates"]
